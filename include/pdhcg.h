@@ -1,0 +1,223 @@
+/*
+ * pdhcg.h -- C ABI of the MI355X restarted-PDHG solver for conic convex QP.
+ *
+ * Problem (paper, introduction, eq. cqp):
+ *     minimise  1/2 <x, Q x> + <c, x>   subject to  A x = b,  x in K,
+ * with Q = P + R^T D R (implementation section, "General Quadratic
+ * Objective") and K a Cartesian product of free, nonnegative, second-order
+ * (v, t), rotated second-order (v, s, t), exponential (r, s, t) and 3-D power
+ * (x, y, z; exponent alpha) blocks (implementation section, cone list).
+ *
+ * Method (implementation section): primal-first PDHG operator whose primal
+ * step is the conic proximal subproblem (eq. prox-subproblem), solved by one
+ * diagonal-metric projection when Q is diagonal (eq. diagonal-q-metric) or by
+ * Jacobi-preconditioned projected Barzilai-Borwein iterations
+ * (eq. jacobi-bb-step) otherwise; reflected-Halpern epochs (eq. rh-update)
+ * or averaged epochs (Alg. 1); adaptive restart (eq. practical-restart-rule);
+ * PID primal weight (eq. pid-weight); rescaling (Section "Problem
+ * Rescaling"); termination on relative KKT residuals of the unscaled
+ * candidate.
+ *
+ * Conventions
+ *  - All pointers in pdhcg_problem and the x0/y0/x/y/s arguments are HOST
+ *    pointers.  The library deep-copies problem data during setup; the caller
+ *    keeps ownership of every buffer it passes and may free it after the call
+ *    returns.  Handles are opaque, owned by the library, freed by pdhcg_free.
+ *  - Matrices are CSR with int64 row pointers (length rows+1, starting at 0,
+ *    nondecreasing) and int32 column indices in [0, cols); duplicates are
+ *    summed; columns need not be sorted.
+ *  - Cone blocks must tile 0..n-1 contiguously in increasing start order.
+ *  - Functions return PDHCG_OK (0) or a negative error code; nothing throws
+ *    across the ABI and nothing aborts.  Solver outcomes are reported in
+ *    pdhcg_result.status.
+ *  - A handle is not thread-safe; use one handle per host thread.  All device
+ *    work is issued on settings.stream (a hipStream_t passed as void*; NULL
+ *    means the null stream).
+ */
+#ifndef PDHCG_H
+#define PDHCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (function return values) ---------------------------- */
+#define PDHCG_OK        0
+#define PDHCG_E_ARG    -1   /* null pointer, count < 1, bad setting value     */
+#define PDHCG_E_SHAPE  -2   /* n < 1, m < 0, r < 0 or inconsistent sizes      */
+#define PDHCG_E_CSR    -3   /* bad row pointer or column index out of range   */
+#define PDHCG_E_CONE   -4   /* blocks do not tile 0..n-1, bad dim or alpha    */
+#define PDHCG_E_NONSYM -5   /* P not symmetric or D not symmetric             */
+#define PDHCG_E_MEM    -6   /* host or device allocation failed               */
+#define PDHCG_E_HIP    -7   /* a HIP runtime call failed                      */
+#define PDHCG_E_STATE  -8   /* call not valid for this handle                 */
+#define PDHCG_E_NOTRACE -9  /* trace requested but not recorded               */
+
+/* ---- solver status (pdhcg_result.status) ----------------------------- */
+#define PDHCG_OPTIMAL     1
+#define PDHCG_MAX_ITER    2
+#define PDHCG_TIME_LIMIT  3
+#define PDHCG_NUMERICAL   4   /* NaN/Inf detected in the iterates            */
+#define PDHCG_ABORTED     5   /* device-side grid barrier timed out          */
+
+/* ---- cone types ------------------------------------------------------- */
+#define PDHCG_CONE_FREE   0
+#define PDHCG_CONE_NONNEG 1
+#define PDHCG_CONE_SOC    2   /* (v, t): ||v|| <= t, dim >= 1                 */
+#define PDHCG_CONE_RSOC   3   /* (v, s, t): ||v||^2 <= 2 s t, s,t >= 0, dim>=2 */
+#define PDHCG_CONE_EXP    4   /* (r, s, t): cl{s > 0, s e^{r/s} <= t}, dim 3  */
+#define PDHCG_CONE_POW    5   /* (x, y, z): x^a y^(1-a) >= |z|, dim 3,
+                                 alpha in (0, 1)                              */
+
+/* ---- enumerations in settings ---------------------------------------- */
+#define PDHCG_SCHEME_RH   0   /* reflected-Halpern epochs (eq. rh-update)     */
+#define PDHCG_SCHEME_AVG  1   /* averaged epochs of Alg. 1                    */
+#define PDHCG_INNER_JACOBI 0  /* eq. jacobi-bb-step                           */
+#define PDHCG_INNER_EUCLID 1  /* eq. bb-step                                  */
+#define PDHCG_PREC_FP64   0
+#define PDHCG_PREC_FP32   1   /* FP32 matrix sweeps, FP64 state and decisions */
+
+typedef struct {
+    int32_t n;                    /* primal dimension                         */
+    int32_t m;                    /* number of equality rows (may be 0)       */
+    /* A: m x n CSR */
+    const int64_t* A_rowptr;      /* m+1                                      */
+    const int32_t* A_col;         /* A_nnz                                    */
+    const double*  A_val;         /* A_nnz                                    */
+    const double*  b;             /* m                                        */
+    const double*  c;             /* n                                        */
+    /* P: n x n symmetric sparse part of Q, full storage, CSR; nullable       */
+    const int64_t* P_rowptr;
+    const int32_t* P_col;
+    const double*  P_val;
+    /* R: r x n row-major dense factor and D: r x r symmetric; nullable      */
+    int32_t        r;
+    const double*  R;
+    const double*  D;             /* NULL with R != NULL means D = I          */
+    /* cone blocks */
+    int32_t        nblocks;
+    const int32_t* cone_type;     /* PDHCG_CONE_*                             */
+    const int32_t* cone_start;
+    const int32_t* cone_dim;
+    const double*  cone_alpha;    /* read for POW blocks only; nullable       */
+} pdhcg_problem;
+
+typedef struct {
+    /* termination */
+    double  tol;                  /* relative KKT tolerance (default 1e-6)    */
+    int64_t max_iter;             /* outer PDHG evaluations (default 1e6)     */
+    double  time_limit;           /* seconds (default 3600)                   */
+    int32_t check_every;          /* restart / KKT check period (default 64)  */
+    /* scheme */
+    int32_t scheme;               /* PDHCG_SCHEME_* (default RH)              */
+    double  rho;                  /* reflection coefficient in [1/2, 1] (1)   */
+    int32_t avg_epoch;            /* T of Alg. 1 (default 64)                 */
+    /* inner solve (general Q) */
+    int32_t inner;                /* PDHCG_INNER_* (default JACOBI)           */
+    int32_t fixed_inner;          /* >0: exactly that many inner steps        */
+    int32_t j_max;                /* inner step cap (default 500)             */
+    double  eps_in0, gamma_in, eps_min;   /* (1e-3, 5e-4, 1e-9)              */
+    /* restart and primal weight */
+    double  beta_s, beta_n, beta_a;       /* (0.2, 0.8, 0.36)                 */
+    double  pid_beta_i, pid_kp, pid_ki, pid_kd;  /* (0.3, 0.99, 0.01, 0)     */
+    /* rescaling */
+    int32_t scaling;              /* master switch (default 1)                */
+    int32_t ruiz_iters;           /* default 10                               */
+    int32_t pock_chambolle;       /* default 1                                */
+    double  pc_alpha;             /* default 1                                */
+    int32_t bound_objective;      /* default 1                                */
+    /* step size */
+    int32_t power_iters;          /* default 128                              */
+    double  a_norm;               /* >0 overrides the power iteration         */
+    double  omega0;               /* >0 overrides the initial primal weight   */
+    /* execution */
+    int32_t precision;            /* PDHCG_PREC_* (default FP64)              */
+    int32_t trace_iters;          /* record the first k outer iterations      */
+    int32_t block_dim;            /* 0 = auto                                 */
+    int32_t grid_dim;             /* 0 = auto                                 */
+    int32_t lanes_at;             /* lanes per row of A^T / P (0 = auto)      */
+    int32_t lanes_a;              /* lanes per row of A (0 = auto)            */
+    int32_t host_poll;            /* outer iterations per launch (default 512)*/
+    void*   stream;               /* hipStream_t                              */
+    int32_t verbose;
+} pdhcg_settings;
+
+typedef struct {
+    int32_t status;               /* PDHCG_OPTIMAL ... PDHCG_ABORTED          */
+    int64_t iterations;           /* outer PDHG evaluations                   */
+    int64_t inner_iterations;     /* projected-BB steps summed over all       */
+    int64_t restarts;
+    double  rel_primal, rel_dual, rel_gap;
+    double  primal_obj, dual_obj;
+    double  setup_s, solve_s;
+    double  omega;                /* final primal weight                      */
+    double  a_norm;               /* ||A^||_2 used for the step size          */
+    /* caller-allocated host outputs, nullable: x[n], y[m], s[n] (dual slack
+       s = Qx + c - A^T y of the original problem)                            */
+    double* x;
+    double* y;
+    double* s;
+} pdhcg_result;
+
+/* Per-iteration record for parity checks, in the library's scaled space
+ * (x^ = S_x x / nu_b, y^ = y / (nu_c S_y); the scale vectors are returned by
+ * pdhcg_get_scaling).  Arrays are caller-allocated host buffers of length
+ * count*n (x, wx) and count*m (y, wy), count*1 for the scalars; iteration k
+ * occupies the k-th slice.  x, y: Halpern state before the evaluation;
+ * wx, wy: PDHG candidate.                                                   */
+typedef struct {
+    int32_t count;                /* in: slices provided; out: recorded       */
+    double* x;  double* y;  double* wx;  double* wy;
+    double* tau; double* sigma; double* omega; double* eps_in;
+    int32_t* inner; int32_t* restart; int32_t* check; double* E;
+} pdhcg_trace;
+
+/* Fill *s with the defaults of the paper's Table practical-defaults and the
+ * library's readings (check_every 64, J_max 500, 128 power iterations).
+ * Returns PDHCG_E_ARG if s is NULL.                                          */
+int pdhcg_default_settings(pdhcg_settings* s);
+
+/* Validate `count` problems, rescale them (Section "Problem Rescaling"),
+ * build A^T, estimate ||A^||_2 (eq. practical-stepsizes), upload everything
+ * to the current HIP device and return a handle in *out.  count > 1 prepares
+ * a batch for pdhcg_solve_batch.  On error *out is left NULL.               */
+int pdhcg_setup(const pdhcg_problem* probs, int32_t count,
+                const pdhcg_settings* s, void** out);
+
+/* Solve the single problem of handle h (count == 1) from the optional warm
+ * start (x0[n], y0[m], original space; NULL means zero).  Fills *res
+ * (status, counters, residuals, objectives, timings) and, when non-NULL,
+ * res->x, res->y, res->s.  Returns PDHCG_E_STATE for a batch handle.        */
+int pdhcg_solve(void* h, const double* x0, const double* y0, pdhcg_result* res);
+
+/* Solve every problem of a batch handle in one persistent launch, one
+ * workgroup per instance with per-instance step sizes, restarts and inner
+ * tolerances.  x0s/y0s: NULL or arrays of `count` host pointers (each may be
+ * NULL).  res: array of `count` results (their x/y/s pointers may be set).  */
+int pdhcg_solve_batch(void* h, const double* const* x0s, const double* const* y0s,
+                      pdhcg_result* res);
+
+/* Copy the recorded iterations of instance `inst` into *t.  Requires
+ * settings.trace_iters > 0 at setup; PDHCG_E_NOTRACE otherwise.             */
+int pdhcg_get_trace(void* h, int32_t inst, pdhcg_trace* t);
+
+/* Copy the scaling of instance `inst`: Sx[n], Sy[m] (nullable) and the
+ * bound/objective factors nu_b, nu_c (nullable); also eta and omega0.       */
+int pdhcg_get_scaling(void* h, int32_t inst, double* Sx, double* Sy,
+                      double* nu_b, double* nu_c, double* eta, double* omega0);
+
+/* Release every host and device resource of h (NULL is a no-op).          */
+void pdhcg_free(void* h);
+
+/* Static description of an error code or status.                          */
+const char* pdhcg_strerror(int code);
+
+/* Library version string.                                                  */
+const char* pdhcg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHCG_H */

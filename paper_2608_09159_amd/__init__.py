@@ -1,0 +1,272 @@
+"""Python binding of libpdhcg.so, the MI355X (gfx950) restarted-PDHG solver for
+conic convex QP.
+
+The binding only marshals arguments: every step of the solve runs in the HIP
+library.  There is no CPU fallback; importing works without the library, but
+any call raises ``RuntimeError`` when ``libpdhcg.so`` is missing.
+
+Functions mirror the C ABI of ``include/pdhcg.h``:
+
+    default_settings(**overrides) -> Settings
+    setup(problem, settings) -> Handle       (pdhcg_setup, count == 1)
+    Handle.solve(x0=None, y0=None) -> dict    (pdhcg_solve)
+    Handle.trace(count) -> dict               (pdhcg_get_trace)
+    Handle.scaling() -> dict                  (pdhcg_get_scaling)
+    Handle.free()                             (pdhcg_free)
+
+``problem`` is any object with the fields of ``instances.Problem``
+(n, m, A as scipy CSR, b, c, optional P / R / D, cones as
+(type, start, dim, alpha) tuples with type in CONE_CODES).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdhcg.so")
+
+CONE_CODES = {"free": 0, "nonneg": 1, "soc": 2, "rsoc": 3, "exp": 4, "pow": 5}
+STATUS = {1: "OPTIMAL", 2: "MAX_ITER", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "ABORTED"}
+SCHEMES = {"rh": 0, "avg": 1}
+INNER = {"jacobi": 0, "euclid": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32),
+                ("A_rowptr", _i64p), ("A_col", _i32p), ("A_val", _dp),
+                ("b", _dp), ("c", _dp),
+                ("P_rowptr", _i64p), ("P_col", _i32p), ("P_val", _dp),
+                ("r", C.c_int32), ("R", _dp), ("D", _dp),
+                ("nblocks", C.c_int32), ("cone_type", _i32p), ("cone_start", _i32p),
+                ("cone_dim", _i32p), ("cone_alpha", _dp)]
+
+
+class Settings(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit", C.c_double),
+                ("check_every", C.c_int32), ("scheme", C.c_int32), ("rho", C.c_double),
+                ("avg_epoch", C.c_int32), ("inner", C.c_int32), ("fixed_inner", C.c_int32),
+                ("j_max", C.c_int32), ("eps_in0", C.c_double), ("gamma_in", C.c_double),
+                ("eps_min", C.c_double), ("beta_s", C.c_double), ("beta_n", C.c_double),
+                ("beta_a", C.c_double), ("pid_beta_i", C.c_double), ("pid_kp", C.c_double),
+                ("pid_ki", C.c_double), ("pid_kd", C.c_double), ("scaling", C.c_int32),
+                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32),
+                ("pc_alpha", C.c_double), ("bound_objective", C.c_int32),
+                ("power_iters", C.c_int32), ("a_norm", C.c_double), ("omega0", C.c_double),
+                ("precision", C.c_int32), ("trace_iters", C.c_int32), ("block_dim", C.c_int32),
+                ("grid_dim", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
+                ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int64),
+                ("inner_iterations", C.c_int64), ("restarts", C.c_int64),
+                ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double),
+                ("setup_s", C.c_double), ("solve_s", C.c_double), ("omega", C.c_double),
+                ("a_norm", C.c_double), ("x", _dp), ("y", _dp), ("s", _dp)]
+
+
+class TraceC(C.Structure):
+    _fields_ = [("count", C.c_int32), ("x", _dp), ("y", _dp), ("wx", _dp), ("wy", _dp),
+                ("tau", _dp), ("sigma", _dp), ("omega", _dp), ("eps_in", _dp),
+                ("inner", _i32p), ("restart", _i32p), ("check", _i32p), ("E", _dp)]
+
+
+_LIB = None
+
+EXPORTS = ("pdhcg_default_settings", "pdhcg_setup", "pdhcg_solve", "pdhcg_solve_batch",
+           "pdhcg_get_trace", "pdhcg_get_scaling", "pdhcg_free", "pdhcg_strerror",
+           "pdhcg_version")
+
+
+def lib_path():
+    return LIB_PATH
+
+
+def load(path=None):
+    """Load libpdhcg.so (raises RuntimeError if it has not been built)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libpdhcg.so not found at {p}; build it with "
+                           "`python -m paper_2608_09159_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(p)
+    lib.pdhcg_default_settings.argtypes = [C.POINTER(Settings)]
+    lib.pdhcg_setup.argtypes = [C.POINTER(ProblemC), C.c_int32, C.POINTER(Settings),
+                                C.POINTER(C.c_void_p)]
+    lib.pdhcg_solve.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(ResultC)]
+    lib.pdhcg_solve_batch.argtypes = [C.c_void_p, C.POINTER(_dp), C.POINTER(_dp),
+                                      C.POINTER(ResultC)]
+    lib.pdhcg_get_trace.argtypes = [C.c_void_p, C.c_int32, C.POINTER(TraceC)]
+    lib.pdhcg_get_scaling.argtypes = [C.c_void_p, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.pdhcg_free.argtypes = [C.c_void_p]
+    lib.pdhcg_free.restype = None
+    lib.pdhcg_strerror.argtypes = [C.c_int]
+    lib.pdhcg_strerror.restype = C.c_char_p
+    lib.pdhcg_version.restype = C.c_char_p
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = load().pdhcg_strerror(rc).decode()
+        raise RuntimeError(f"{what} failed: {msg} ({rc})")
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    _check(load().pdhcg_default_settings(C.byref(s)), "pdhcg_default_settings")
+    for k, v in kw.items():
+        if k == "scheme":
+            v = SCHEMES[v] if isinstance(v, str) else v
+        elif k == "inner":
+            v = INNER[v] if isinstance(v, str) else v
+        elif k == "precision":
+            v = PRECISION[v] if isinstance(v, str) else v
+        elif k == "stream":
+            v = getattr(v, "cuda_stream", v)
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+class _Marshalled:
+    """Keeps the numpy buffers alive for the duration of pdhcg_setup."""
+
+    def __init__(self, prob):
+        A = prob.A.tocsr()
+        self.keep = []
+
+        def arr(x, dt):
+            if x is None:
+                return None
+            y = np.ascontiguousarray(x, dtype=dt)
+            self.keep.append(y)
+            return y
+
+        pc = ProblemC()
+        pc.n, pc.m = int(prob.n), int(prob.m)
+        pc.A_rowptr = _ptr(arr(A.indptr, np.int64), C.c_int64)
+        pc.A_col = _ptr(arr(A.indices, np.int32), C.c_int32)
+        pc.A_val = _ptr(arr(A.data, np.float64), C.c_double)
+        pc.b = _ptr(arr(prob.b, np.float64), C.c_double)
+        pc.c = _ptr(arr(prob.c, np.float64), C.c_double)
+        if prob.P is not None:
+            P = prob.P.tocsr()
+            pc.P_rowptr = _ptr(arr(P.indptr, np.int64), C.c_int64)
+            pc.P_col = _ptr(arr(P.indices, np.int32), C.c_int32)
+            pc.P_val = _ptr(arr(P.data, np.float64), C.c_double)
+        if prob.R is not None:
+            pc.r = int(prob.R.shape[0])
+            pc.R = _ptr(arr(prob.R, np.float64), C.c_double)
+            pc.D = _ptr(arr(prob.D, np.float64), C.c_double) if prob.D is not None else None
+        ct = np.array([CONE_CODES[k] for k, _, _, _ in prob.cones], dtype=np.int32)
+        pc.nblocks = len(prob.cones)
+        pc.cone_type = _ptr(arr(ct, np.int32), C.c_int32)
+        pc.cone_start = _ptr(arr([s for _, s, _, _ in prob.cones], np.int32), C.c_int32)
+        pc.cone_dim = _ptr(arr([d for _, _, d, _ in prob.cones], np.int32), C.c_int32)
+        pc.cone_alpha = _ptr(arr([a for _, _, _, a in prob.cones], np.float64), C.c_double)
+        self.pc = pc
+
+
+class Handle:
+    def __init__(self, ptr, prob, settings):
+        self.ptr = ptr
+        self.n, self.m = int(prob.n), int(prob.m)
+        self.settings = settings
+
+    def solve(self, x0=None, y0=None, want_s=False):
+        lib = load()
+        res = ResultC()
+        x = np.zeros(self.n)
+        y = np.zeros(self.m)
+        s = np.zeros(self.n) if want_s else None
+        res.x = _ptr(x, C.c_double)
+        res.y = _ptr(y, C.c_double)
+        res.s = _ptr(s, C.c_double) if want_s else None
+        x0a = np.ascontiguousarray(x0, dtype=np.float64) if x0 is not None else None
+        y0a = np.ascontiguousarray(y0, dtype=np.float64) if y0 is not None else None
+        _check(lib.pdhcg_solve(self.ptr, _ptr(x0a, C.c_double), _ptr(y0a, C.c_double),
+                               C.byref(res)), "pdhcg_solve")
+        out = dict(status=STATUS.get(res.status, str(res.status)), iterations=res.iterations,
+                   inner_iterations=res.inner_iterations, restarts=res.restarts,
+                   rel_primal=res.rel_primal, rel_dual=res.rel_dual, rel_gap=res.rel_gap,
+                   primal_obj=res.primal_obj, dual_obj=res.dual_obj, setup_s=res.setup_s,
+                   solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y)
+        if want_s:
+            out["s"] = s
+        return out
+
+    def trace(self, count):
+        lib = load()
+        t = TraceC()
+        t.count = count
+        bufs = dict(x=np.zeros((count, self.n)), y=np.zeros((count, self.m)),
+                    wx=np.zeros((count, self.n)), wy=np.zeros((count, self.m)),
+                    tau=np.zeros(count), sigma=np.zeros(count), omega=np.zeros(count),
+                    eps_in=np.zeros(count), E=np.zeros(count))
+        ibufs = dict(inner=np.zeros(count, np.int32), restart=np.zeros(count, np.int32),
+                     check=np.zeros(count, np.int32))
+        for k, v in bufs.items():
+            setattr(t, k, _ptr(v, C.c_double))
+        for k, v in ibufs.items():
+            setattr(t, k, _ptr(v, C.c_int32))
+        _check(lib.pdhcg_get_trace(self.ptr, 0, C.byref(t)), "pdhcg_get_trace")
+        out = {k: v[:t.count] for k, v in {**bufs, **ibufs}.items()}
+        out["count"] = t.count
+        return out
+
+    def scaling(self):
+        lib = load()
+        Sx, Sy = np.zeros(self.n), np.zeros(self.m)
+        vals = [C.c_double() for _ in range(4)]
+        _check(lib.pdhcg_get_scaling(self.ptr, 0, _ptr(Sx, C.c_double), _ptr(Sy, C.c_double),
+                                     *[C.pointer(v) for v in vals]), "pdhcg_get_scaling")
+        return dict(Sx=Sx, Sy=Sy, nu_b=vals[0].value, nu_c=vals[1].value, eta=vals[2].value,
+                    omega0=vals[3].value)
+
+    def free(self):
+        if self.ptr:
+            load().pdhcg_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def setup(prob, settings=None, **kw) -> Handle:
+    lib = load()
+    s = settings if settings is not None else default_settings(**kw)
+    m = _Marshalled(prob)
+    h = C.c_void_p()
+    _check(lib.pdhcg_setup(C.byref(m.pc), 1, C.byref(s), C.byref(h)), "pdhcg_setup")
+    return Handle(h.value, prob, s)
+
+
+def solve(prob, x0=None, y0=None, want_s=False, **kw):
+    """Convenience: setup + solve + free."""
+    h = setup(prob, **kw)
+    try:
+        return h.solve(x0, y0, want_s=want_s)
+    finally:
+        h.free()

@@ -1,0 +1,125 @@
+// Internal structures shared by the host setup, the driver and the kernels.
+#pragma once
+#include <stdint.h>
+
+#include "pdhcg.h"
+
+namespace pdhcg {
+
+constexpr int RMAX = 32;          // largest supported rank of the dense factor R
+constexpr int MAX_BLOCK = 1024;
+
+// per-coordinate kind used by elementwise passes
+enum : uint8_t { CT_FREE = 0, CT_NONNEG = 1, CT_CONE = 2 };
+
+// reduction slots (each slot holds one double per workgroup)
+enum Slot : int {
+  SL_DELTA2 = 0,   // ||u_new - u||^2                (inner stop test)
+  SL_SJS,          // <s, J s>                       (BB numerator)
+  SL_SDG,          // <s, dg>                        (BB denominator)
+  SL_SS,           // ||s||^2                        (Euclidean BB numerator)
+  SL_DX2,          // ||x - w_x||^2                  (restart metric)
+  SL_DY2,          // ||y - w_y||^2
+  SL_ADXDY,        // <A(x - w_x), y - w_y>
+  SL_XMOV2,        // ||x_new - x||^2                (inner tolerance)
+  SL_RP2,          // ||A x - b||^2 (unscaled)
+  SL_RD2,          // ||Pi_K(-s)||^2 (unscaled)
+  SL_XQX,          // <x, Q x>   (scaled)
+  SL_CX,           // <c, x>     (scaled)
+  SL_BY,           // <b, y>     (scaled)
+  SL_MOVX2,        // ||w_x - a_x||^2                (PID)
+  SL_MOVY2,        // ||w_y - a_y||^2
+  SL_NAN,          // count of non-finite values
+  SL_QMAX,         // unused slot kept for alignment
+  SL_H0,           // R u : RMAX slots
+  SL_COUNT = SL_H0 + RMAX
+};
+
+struct DevProblem {
+  int n, m, r;
+  int at_lanes, a_lanes;
+  const int64_t* A_ptr;  const int* A_col;  const double* A_val;
+  const int64_t* AT_ptr; const int* AT_col; const double* AT_val;
+  const int64_t* P_ptr;  const int* P_col;  const double* P_val;  // nullable
+  const double* R;       // r x n row-major (scaled)
+  const double* Dm;      // r x r (scaled)
+  const double* b;       // m (scaled)
+  const double* c;       // n (scaled)
+  const double* qd;      // n diag(Q^)
+  const double* Sx;      // n
+  const double* Sy;      // m
+  const uint8_t* ctype;  // n
+  int n_wave, n_lane;
+  const int* wave_start; const int* wave_dim; const uint8_t* wave_type;
+  const uint8_t* wave_euclid;
+  const int* lane_start; const uint8_t* lane_type; const double* lane_alpha;
+  const uint8_t* lane_euclid;
+  double nu_b, nu_c, norm_b, norm_c;   // norm_b, norm_c: ||b||, ||c|| of the original data
+  double eta, omega0;
+  int q_diag;            // Q^ diagonal (includes Q = 0): one metric projection per prox
+};
+
+struct DevVec {
+  double *x, *y, *ax, *ay, *wx, *wy;
+  double *Ax, *Aa, *Aw;          // A^ x, A^ a, A^ w_x (m)
+  double *v, *u, *up, *g, *gp;   // inner-solve vectors (n)
+  double *zb;                    // pre-projection buffer (n)
+  double *s;                     // KKT dual slack (n)
+  double *xb, *yb, *Axb;         // averaged scheme
+  double *partials;              // SL_COUNT x G
+};
+
+struct DevSettings {
+  double tol;
+  long long max_iter;
+  int check_every;
+  int scheme;
+  double rho;
+  int avg_epoch;
+  int inner;
+  int fixed_inner;
+  int j_max;
+  double eps_in0, gamma_in, eps_min;
+  double beta_s, beta_n, beta_a;
+  double pid_beta_i, pid_kp, pid_ki, pid_kd;
+  int trace_iters;
+};
+
+// scalar state persisted in device memory between launches
+struct Ctl {
+  double omega, eps_in, E0, Eprev, pid_I, e_prev;
+  double rel_p, rel_d, rel_gap, pobj, dobj, lastE;
+  long long k, ktot, inner_total, restarts;
+  int status;       // 0 running, else PDHCG_* status
+  int started;
+  int pad0, pad1;
+  double hx[RMAX];  // R^ x of the current Halpern primal state
+  double hxb[RMAX]; // R^ xbar (averaged scheme)
+};
+
+struct TraceBufs {
+  int cap;                       // 0 = off
+  double *x, *y, *wx, *wy;       // cap*n, cap*m
+  double *sc;                    // cap * 8 scalars
+};
+
+struct Barrier {
+  unsigned count;
+  unsigned gen;
+  int abort;
+  int pad;
+};
+
+struct KArgs {
+  DevProblem P;
+  DevVec V;
+  DevSettings S;
+  Ctl* ctl;
+  Barrier* bar;
+  TraceBufs T;
+  long long stop_at;   // return to the host when ktot reaches this
+  unsigned long long spin_limit;  // grid-barrier wait bound, wall-clock ticks
+  double qmax;         // max_i diag(Q^)_i (first Euclidean BB step)
+};
+
+}  // namespace pdhcg

@@ -1,0 +1,303 @@
+// Host-side validation, canonicalisation and rescaling of one problem.
+//
+// Rescaling follows the paper's Section "Problem Rescaling"
+// (eq. problem-rescaling, eq. cone-scaling-candidates,
+// eq. cone-preserving-scaling) with the defaults of Table practical-defaults:
+// Ruiz passes (column candidate sqrt(max_l |A_li|)), one Pock-Chambolle pass
+// (column candidate sqrt(sum_l |A_li|^(2-alpha))), rows by the same
+// coordinatewise rule (sqrt(max_i |A_li|), sqrt(sum_i |A_li|^alpha)), cone
+// blocks sharing one factor (block maximum for Ruiz, block root-mean-square
+// for Pock-Chambolle), zero rows and columns keeping factor 1, then
+// bound-objective normalisation b^ = b~/(||b~|| + 1), c^ = c~/(||c~|| + 1)
+// with Q^ = Q~ (||b~|| + 1)/(||c~|| + 1) so that x^ = x~/nu_b keeps the
+// objective proportional.
+#include "host_setup.hpp"
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace pdhcg {
+
+namespace {
+
+int canon_csr(int64_t rows, int64_t cols, const int64_t* ptr, const int32_t* col,
+              const double* val, Csr& out) {
+  out.rows = rows;
+  out.cols = cols;
+  out.ptr.assign(rows + 1, 0);
+  if (rows == 0) return PDHCG_OK;
+  if (!ptr) return PDHCG_E_ARG;
+  if (ptr[0] != 0) return PDHCG_E_CSR;
+  for (int64_t i = 0; i < rows; ++i)
+    if (ptr[i + 1] < ptr[i]) return PDHCG_E_CSR;
+  int64_t nnz = ptr[rows];
+  if (nnz > 0 && (!col || !val)) return PDHCG_E_ARG;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (col[k] < 0 || col[k] >= cols) return PDHCG_E_CSR;
+  out.col.reserve(nnz);
+  out.val.reserve(nnz);
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < rows; ++i) {
+    row.clear();
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) row.emplace_back(col[k], val[k]);
+    std::sort(row.begin(), row.end(),
+              [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                return a.first < b.first;
+              });
+    for (size_t k = 0; k < row.size();) {
+      int32_t j = row[k].first;
+      double acc = 0.0;
+      while (k < row.size() && row[k].first == j) acc += row[k++].second;
+      out.col.push_back(j);
+      out.val.push_back(acc);
+    }
+    out.ptr[i + 1] = (int64_t)out.col.size();
+  }
+  return PDHCG_OK;
+}
+
+Csr transpose(const Csr& a) {
+  Csr t;
+  t.rows = a.cols;
+  t.cols = a.rows;
+  t.ptr.assign(t.rows + 1, 0);
+  for (int64_t k = 0; k < a.nnz(); ++k) t.ptr[a.col[k] + 1]++;
+  for (int64_t i = 0; i < t.rows; ++i) t.ptr[i + 1] += t.ptr[i];
+  t.col.resize(a.nnz());
+  t.val.resize(a.nnz());
+  std::vector<int64_t> pos(t.ptr.begin(), t.ptr.end() - 1);
+  for (int64_t i = 0; i < a.rows; ++i)
+    for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
+      int64_t d = pos[a.col[k]]++;
+      t.col[d] = (int32_t)i;
+      t.val[d] = a.val[k];
+    }
+  return t;
+}
+
+double norm2(const std::vector<double>& v) {
+  double s = 0.0;
+  for (double x : v) s += x * x;
+  return std::sqrt(s);
+}
+
+// divide entry (l, i) by row[l] * col[i]
+void apply_scaling(Csr& a, const std::vector<double>& row, const std::vector<double>& col) {
+  for (int64_t l = 0; l < a.rows; ++l)
+    for (int64_t k = a.ptr[l]; k < a.ptr[l + 1]; ++k) a.val[k] = a.val[k] / (row[l] * col[a.col[k]]);
+}
+
+}  // namespace
+
+int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance& H) {
+  if (p.n < 1 || p.m < 0 || p.r < 0) return PDHCG_E_SHAPE;
+  if (p.r > RMAX) return PDHCG_E_SHAPE;
+  if (!p.c || (p.m > 0 && (!p.b || !p.A_rowptr))) return PDHCG_E_ARG;
+  if (p.nblocks < 1 || !p.cone_type || !p.cone_start || !p.cone_dim) return PDHCG_E_CONE;
+  const int n = p.n, m = p.m;
+  H.n = n;
+  H.m = m;
+
+  // ---- cones: contiguous tiling of 0..n-1 --------------------------------
+  H.cones.clear();
+  int pos = 0;
+  for (int j = 0; j < p.nblocks; ++j) {
+    ConeBlock cb{p.cone_type[j], p.cone_start[j], p.cone_dim[j],
+                 p.cone_alpha ? p.cone_alpha[j] : 0.0};
+    if (cb.start != pos || cb.dim < 1 || cb.start + cb.dim > n) return PDHCG_E_CONE;
+    switch (cb.type) {
+      case PDHCG_CONE_FREE:
+      case PDHCG_CONE_NONNEG:
+      case PDHCG_CONE_SOC:
+        break;
+      case PDHCG_CONE_RSOC:
+        if (cb.dim < 2) return PDHCG_E_CONE;
+        break;
+      case PDHCG_CONE_EXP:
+        if (cb.dim != 3) return PDHCG_E_CONE;
+        break;
+      case PDHCG_CONE_POW:
+        if (cb.dim != 3 || !(cb.alpha > 0.0 && cb.alpha < 1.0)) return PDHCG_E_CONE;
+        break;
+      default:
+        return PDHCG_E_CONE;
+    }
+    H.cones.push_back(cb);
+    pos += cb.dim;
+  }
+  if (pos != n) return PDHCG_E_CONE;
+
+  // ---- matrices ------------------------------------------------------------
+  int rc = canon_csr(m, n, p.A_rowptr, p.A_col, p.A_val, H.A);
+  if (rc) return rc;
+  bool hasP = p.P_rowptr != nullptr;
+  if (hasP) {
+    rc = canon_csr(n, n, p.P_rowptr, p.P_col, p.P_val, H.P);
+    if (rc) return rc;
+    // symmetry: P == P^T up to a relative 1e-12
+    Csr PT = transpose(H.P);
+    double pmax = 0.0;
+    for (double v : H.P.val) pmax = std::max(pmax, std::fabs(v));
+    if (PT.ptr != H.P.ptr || PT.col != H.P.col) return PDHCG_E_NONSYM;
+    for (int64_t k = 0; k < H.P.nnz(); ++k)
+      if (std::fabs(PT.val[k] - H.P.val[k]) > 1e-12 * std::max(1.0, pmax)) return PDHCG_E_NONSYM;
+  } else {
+    H.P = Csr();
+  }
+  const int r = (p.R != nullptr) ? p.r : 0;
+  H.r = r;
+  if (r > 0) {
+    H.R.assign(p.R, p.R + (size_t)r * n);
+    H.D.assign((size_t)r * r, 0.0);
+    if (p.D) {
+      for (int a = 0; a < r; ++a)
+        for (int b2 = 0; b2 < r; ++b2) {
+          double dab = p.D[a * r + b2], dba = p.D[b2 * r + a];
+          if (std::fabs(dab - dba) > 1e-12 * std::max(1.0, std::fabs(dab))) return PDHCG_E_NONSYM;
+          H.D[a * r + b2] = dab;
+        }
+    } else {
+      for (int a = 0; a < r; ++a) H.D[a * r + a] = 1.0;
+    }
+  }
+  H.b.assign(p.b ? p.b : nullptr, p.b ? p.b + m : nullptr);
+  H.c.assign(p.c, p.c + n);
+  for (double v : H.b) if (!std::isfinite(v)) return PDHCG_E_ARG;
+  for (double v : H.c) if (!std::isfinite(v)) return PDHCG_E_ARG;
+  H.norm_b = norm2(H.b);
+  H.norm_c = norm2(H.c);
+
+  // ---- rescaling -------------------------------------------------------------
+  H.Sx.assign(n, 1.0);
+  H.Sy.assign(m, 1.0);
+  std::vector<std::pair<int, int>> blocks;  // non-elementwise cone blocks
+  for (const auto& cb : H.cones)
+    if (cb.type != PDHCG_CONE_FREE && cb.type != PDHCG_CONE_NONNEG) blocks.emplace_back(cb.start, cb.dim);
+  Csr& A = H.A;
+  if (s.scaling) {
+    std::vector<double> row(m), col(n);
+    for (int it = 0; it < s.ruiz_iters; ++it) {
+      std::fill(row.begin(), row.end(), 0.0);
+      std::fill(col.begin(), col.end(), 0.0);
+      for (int64_t l = 0; l < m; ++l)
+        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
+          double a = std::fabs(A.val[k]);
+          row[l] = std::max(row[l], a);
+          col[A.col[k]] = std::max(col[A.col[k]], a);
+        }
+      for (auto& v : row) v = std::sqrt(v);
+      for (auto& v : col) v = std::sqrt(v);
+      for (auto& bk : blocks) {
+        double mx = 0.0;
+        for (int i = bk.first; i < bk.first + bk.second; ++i) mx = std::max(mx, col[i]);
+        for (int i = bk.first; i < bk.first + bk.second; ++i) col[i] = mx;
+      }
+      for (auto& v : row) if (v == 0.0) v = 1.0;
+      for (auto& v : col) if (v == 0.0) v = 1.0;
+      apply_scaling(A, row, col);
+      for (int l = 0; l < m; ++l) H.Sy[l] /= row[l];
+      for (int i = 0; i < n; ++i) H.Sx[i] *= col[i];
+    }
+    if (s.pock_chambolle) {
+      const double al = s.pc_alpha;
+      std::fill(row.begin(), row.end(), 0.0);
+      std::fill(col.begin(), col.end(), 0.0);
+      for (int64_t l = 0; l < m; ++l)
+        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
+          double a = std::fabs(A.val[k]);
+          row[l] += std::pow(a, al);
+          col[A.col[k]] += std::pow(a, 2.0 - al);
+        }
+      for (auto& v : row) v = std::sqrt(v);
+      for (auto& v : col) v = std::sqrt(v);
+      for (auto& bk : blocks) {
+        double ss = 0.0;
+        for (int i = bk.first; i < bk.first + bk.second; ++i) ss += col[i] * col[i];
+        double rms = std::sqrt(ss / bk.second);
+        for (int i = bk.first; i < bk.first + bk.second; ++i) col[i] = rms;
+      }
+      for (auto& v : row) if (v == 0.0) v = 1.0;
+      for (auto& v : col) if (v == 0.0) v = 1.0;
+      apply_scaling(A, row, col);
+      for (int l = 0; l < m; ++l) H.Sy[l] /= row[l];
+      for (int i = 0; i < n; ++i) H.Sx[i] *= col[i];
+    }
+  }
+  // c~ = S_x^-1 c, b~ = S_y b, P~ = S_x^-1 P S_x^-1, R~ = R S_x^-1
+  for (int i = 0; i < n; ++i) H.c[i] /= H.Sx[i];
+  for (int l = 0; l < m; ++l) H.b[l] *= H.Sy[l];
+  if (hasP)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k)
+        H.P.val[k] = H.P.val[k] / (H.Sx[i] * H.Sx[H.P.col[k]]);
+  for (int a = 0; a < r; ++a)
+    for (int i = 0; i < n; ++i) H.R[(size_t)a * n + i] /= H.Sx[i];
+  H.nu_b = H.nu_c = 1.0;
+  if (s.scaling && s.bound_objective) {
+    H.nu_b = norm2(H.b) + 1.0;
+    H.nu_c = norm2(H.c) + 1.0;
+  }
+  for (auto& v : H.b) v /= H.nu_b;
+  for (auto& v : H.c) v /= H.nu_c;
+  const double qs = H.nu_b / H.nu_c;
+  for (auto& v : H.P.val) v *= qs;
+  for (auto& v : H.D) v *= qs;
+
+  // ---- transpose, diagonal of Q^, structure flags -------------------------
+  H.AT = transpose(A);
+  H.qdiag.assign(n, 0.0);
+  H.q_diag = (r == 0);
+  if (hasP)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) {
+        if (H.P.col[k] == i) H.qdiag[i] += H.P.val[k];
+        else H.q_diag = false;
+      }
+  for (int i = 0; i < n && r > 0; ++i) {
+    double acc = 0.0;
+    for (int a = 0; a < r; ++a) {
+      double ra = H.R[(size_t)a * n + i];
+      double t = 0.0;
+      for (int b2 = 0; b2 < r; ++b2) t += H.D[a * r + b2] * H.R[(size_t)b2 * n + i];
+      acc += ra * t;
+    }
+    H.qdiag[i] += acc;
+  }
+
+  // ---- cone work items ---------------------------------------------------------
+  H.ctype.assign(n, CT_CONE);
+  H.wave_start.clear(); H.wave_dim.clear(); H.wave_type.clear(); H.wave_euclid.clear();
+  H.lane_start.clear(); H.lane_type.clear(); H.lane_euclid.clear(); H.lane_alpha.clear();
+  for (const auto& cb : H.cones) {
+    bool euclid = true;
+    for (int i = cb.start + 1; i < cb.start + cb.dim; ++i)
+      if (H.qdiag[i] != H.qdiag[cb.start]) euclid = false;
+    switch (cb.type) {
+      case PDHCG_CONE_FREE:
+        for (int i = cb.start; i < cb.start + cb.dim; ++i) H.ctype[i] = CT_FREE;
+        break;
+      case PDHCG_CONE_NONNEG:
+        for (int i = cb.start; i < cb.start + cb.dim; ++i) H.ctype[i] = CT_NONNEG;
+        break;
+      case PDHCG_CONE_SOC:
+      case PDHCG_CONE_RSOC:
+        H.wave_start.push_back(cb.start);
+        H.wave_dim.push_back(cb.dim);
+        H.wave_type.push_back((uint8_t)cb.type);
+        H.wave_euclid.push_back(euclid ? 1 : 0);
+        break;
+      default:
+        H.lane_start.push_back(cb.start);
+        H.lane_type.push_back((uint8_t)cb.type);
+        H.lane_alpha.push_back(cb.alpha);
+        H.lane_euclid.push_back(euclid ? 1 : 0);
+        break;
+    }
+  }
+  return PDHCG_OK;
+}
+
+}  // namespace pdhcg

@@ -1,0 +1,46 @@
+// Host-side problem validation and rescaling.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "pdhcg.h"
+
+namespace pdhcg {
+
+struct Csr {
+  int64_t rows = 0, cols = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+struct ConeBlock {
+  int type, start, dim;
+  double alpha;
+};
+
+// One problem after validation and rescaling (Section "Problem Rescaling").
+struct HostInstance {
+  int n = 0, m = 0, r = 0;
+  Csr A, AT, P;             // scaled A^, its transpose, scaled P^ (rows==0: absent)
+  std::vector<double> R, D; // scaled R^ (r x n) and D^ (r x r)
+  std::vector<double> b, c; // scaled
+  std::vector<double> Sx, Sy, qdiag;
+  double nu_b = 1, nu_c = 1;
+  double norm_b = 0, norm_c = 0;  // of the original data
+  bool q_diag = true;
+  std::vector<ConeBlock> cones;
+  // per-coordinate kind and cone work items
+  std::vector<uint8_t> ctype;
+  std::vector<int> wave_start, wave_dim;
+  std::vector<uint8_t> wave_type, wave_euclid;
+  std::vector<int> lane_start;
+  std::vector<uint8_t> lane_type, lane_euclid;
+  std::vector<double> lane_alpha;
+};
+
+int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance& out);
+
+}  // namespace pdhcg
