@@ -27,6 +27,7 @@ Passages followed
 
 Readings where the paper is silent (each also listed in the design doc):
 * ||A||_2 by 128 power iterations on A^T A from 1/sqrt(n) (overridable);
+  a zero estimate (A = 0 or no rows) is replaced by 1;
 * omega_0 = ||c^||/||b^|| when both exceed 1e-10, else 1 (overridable);
 * start z = (Pi_K(x0^), y0^) or zero; the inner solve starts at the Halpern
   primal state x; first inner step uses alpha = 1 (Jacobi) or
@@ -179,6 +180,8 @@ def setup(prob, st: Settings = None):
     proj = Projector(prob.cones, prob.n)
     euclid_blocks = proj.const_blocks(q.diag)
     a_norm = st.a_norm if st.a_norm > 0 else power_norm(sc.A, st.power_iters)
+    if not a_norm > 0:       # A = 0 or no rows: any step size keeps tau sigma ||A||^2 < 1
+        a_norm = 1.0
     eta = 0.998 / a_norm
     nb, nc = float(np.linalg.norm(sc.b)), float(np.linalg.norm(sc.c))
     if st.omega0 > 0:

@@ -76,7 +76,7 @@ def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
     Sx = np.ones(n)
     Sy = np.ones(m)
     blocks = _cone_blocks(prob.cones)
-    if enabled:
+    if enabled and m > 0:        # no rows: every factor is 1
         for _ in range(ruiz_iters):
             absA = abs(A)
             col = np.sqrt(np.asarray(absA.max(axis=0).todense()).ravel())

@@ -329,26 +329,33 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   if (h->s.host_poll <= 0) h->s.host_poll = 512;
   h->ds = to_dev(h->s);
   h->stream = (hipStream_t)s->stream;
-  int dev = 0, rate_khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
-    delete h;
-    return PDHCG_E_HIP;
-  }
-  if (rate_khz <= 0) rate_khz = 100000;
-  h->spin_limit = (unsigned long long)rate_khz * 1000ull * 4ull;   // 4 s
+  // host-side validation and rescaling first: invalid input is reported
+  // without touching the device
   for (int i = 0; i < count; ++i) {
     Instance* I = new (std::nothrow) Instance();
     if (!I) { pdhcg_free(h); return PDHCG_E_MEM; }
     h->inst.push_back(I);
     int rc = build_instance(probs[i], h->s, I->H);
-    if (rc == PDHCG_OK) rc = upload_instance(h, I);
+    if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
+  }
+  int dev = 0, rate_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+    pdhcg_free(h);
+    return PDHCG_E_HIP;
+  }
+  if (rate_khz <= 0) rate_khz = 100000;
+  h->spin_limit = (unsigned long long)rate_khz * 1000ull * 4ull;   // 4 s
+  for (int i = 0; i < count; ++i) {
+    Instance* I = h->inst[i];
+    int rc = upload_instance(h, I);
     if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
     double an = s->a_norm;
     if (!(an > 0)) {
       rc = power_norm(h, I, &an);
       if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
     }
+    if (!(an > 0)) an = 1.0;   // A = 0 or no rows: the dual step is void
     I->P.eta = 0.998 / an;
     double nb = 0, nc = 0;
     for (double v : I->H.b) nb += v * v;
