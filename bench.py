@@ -1,0 +1,168 @@
+"""Benchmark: time-to-1e-6 relative KKT and PDHG iterations/s of the MI355X
+solver on the mixed-cone SOCP/QCQP workload (n = 1e5, m = 5e4, ~1e6 nnz,
+2000 SOC(20) + 1000 RSOC(10) + 500 EXP + 500 POW + R+, Q = diag + rank-10).
+
+One step = one full solve from a cold start to the tolerance (every row of
+the hot path: prox with Jacobi projected-BB inner loop, batched cone
+projections, A and A^T products, reflected-Halpern update, restarts, device
+KKT checks).  Setup (rescaling, A^T, power iteration) is outside the timed
+region; problem data is resident in HBM when timing starts.
+
+Prints one JSON line.  `--gpus N` with N > 1 is rejected: this build targets a
+single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-6 rel KKT (s) + PDHG iters/s; FP32/batched/warm vs plain FP64"
+
+
+def workload(name):
+    from instances import synth
+    if name == "mixed_cone":
+        return synth.mixed_cone(seed=0), "mixed-cone SOCP/QCQP n=1e5 m=5e4"
+    if name == "tiny_qp":
+        return synth.tiny_qp(0), "tiny QP n=200 m=100"
+    if name == "fisher":
+        return synth.fisher(seed=1_000_001), "Fisher market 1000 buyers x 500 goods (EXP)"
+    if name == "large_sparse_qp":
+        return synth.large_sparse_qp(seed=0), "large sparse QP n=1e7 m=5e6"
+    raise ValueError(name)
+
+
+def bytes_model(prob, iters, inner_total, checks):
+    """Algorithmic HBM bytes of the solver kernel for `iters` outer
+    iterations with `inner_total` projected-BB steps in total (FP64 values,
+    int32 column indices, int64 row pointers; every matrix read once per use,
+    every vector read or written once per pass, ideal gathers)."""
+    n, m = prob.n, prob.m
+    nnzA = prob.A.nnz
+    nnzP = 0 if prob.P is None else prob.P.nnz
+    r = 0 if prob.R is None else prob.R.shape[0]
+    nc = sum(d for k, s, d, a in prob.cones if k not in ("free", "nonneg"))
+    spmv_at = 12 * nnzA + 8 * (n + 1) + 8 * m
+    spmv_a = 12 * nnzA + 8 * (m + 1) + 8 * n
+    spmv_p = (12 * nnzP + 8 * (n + 1) + 8 * n) if nnzP else 0
+    diag_q = r == 0 and (prob.P is None or np.all(prob.P.tocoo().row == prob.P.tocoo().col))
+    p6 = spmv_a + 72 * m + 32 * n
+    if diag_q:
+        per_iter = spmv_at + 33 * n + 24 * nc + p6
+        inner_bytes = 0
+    else:
+        per_iter = spmv_at + spmv_p + 8 * r * n + 57 * n + 32 * nc + 8 * r * nc + p6
+        first = iters                                     # one first step per iteration
+        inner_bytes = max(inner_total - first, 0) * (spmv_p + 16 * r * n + 121 * n + 16 * nc)
+    check_bytes = checks * (spmv_at + spmv_p + 8 * r * n + 41 * n + 24 * nc + 40 * m + 32 * n)
+    return iters * per_iter + inner_bytes + check_bytes
+
+
+def cpu_baseline(prob, budget_s=15.0):
+    """The oracle as it stands, single thread, on the first outer iterations
+    of the same instance; iterations/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle import pdhg
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        S = pdhg.setup(prob, pdhg.Settings())
+        t_setup = time.perf_counter() - t0
+        iters = 2
+        while True:
+            t0 = time.perf_counter()
+            r = pdhg.solve(prob, pdhg.Settings(max_iter=iters), S=S)
+            dt = time.perf_counter() - t0
+            if dt >= budget_s / 3 or iters >= 100000:
+                break
+            iters = int(min(iters * max(2.0, 0.5 * budget_s / max(dt, 1e-3)), 100000))
+    return dict(value=r.iterations / dt, unit="PDHG iters/s", cores=1, kind="oracle",
+                sample=f"first {r.iterations} outer iterations of the same instance "
+                       f"({dt:.1f}s, {r.inner_iterations} inner steps; setup {t_setup:.1f}s "
+                       f"excluded); NumPy/SciPy FP64, BLAS pinned to 1 thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed_cone")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
+              "(the 2-D partition across GPUs is design-only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2608_09159_amd as pkg
+
+    if not os.path.exists(pkg.lib_path()):
+        from paper_2608_09159_amd import build
+        build.build()
+    prob, wname = workload(args.workload)
+    stream = torch.cuda.current_stream()
+    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream)
+    res = None
+    for _ in range(args.warmup):
+        res = h.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        runs.append(h.solve())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h.free()
+    iters = sum(r["iterations"] for r in runs)
+    inner = sum(r["inner_iterations"] for r in runs)
+    ksum = sum(r["kernel_s"] for r in runs)
+    launches = sum(r["kernel_launches"] for r in runs)
+    checks = sum(math.ceil(r["iterations"] / 64) + r["restarts"] + 1 for r in runs)
+    alg_bytes = bytes_model(prob, iters, inner, checks)
+    achieved = alg_bytes / ksum / 1e9
+    last = runs[-1]
+    out = {
+        "metric": METRIC,
+        "value": iters / wall,
+        "unit": "PDHG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "n": prob.n, "m": prob.m, "nnz_A": int(prob.A.nnz),
+                   "tol": args.tol, "precision": "fp64"},
+        "time_to_tol_s": wall / args.steps,
+        "iterations_per_solve": iters / args.steps,
+        "inner_per_solve": inner / args.steps,
+        "status": last["status"],
+        "rel_kkt": max(last["rel_primal"], last["rel_dual"], last["rel_gap"]),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "solve_kernel", "kernel_avg_launch_ms": 1e3 * ksum / launches,
+                     "algorithmic_bytes_per_iteration": alg_bytes / iters},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

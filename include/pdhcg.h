@@ -142,6 +142,8 @@ typedef struct {
     int32_t host_poll;            /* outer iterations per launch (default 512)*/
     void*   stream;               /* hipStream_t                              */
     int32_t verbose;
+    int32_t time_kernels;         /* 1: time every solver launch with HIP
+                                     events on `stream` (result.kernel_s)     */
 } pdhcg_settings;
 
 typedef struct {
@@ -159,6 +161,9 @@ typedef struct {
     double* x;
     double* y;
     double* s;
+    /* device time of the solver launches (settings.time_kernels = 1) */
+    double  kernel_s;
+    int64_t kernel_launches;
 } pdhcg_result;
 
 /* Per-iteration record for parity checks, in the library's scaled space

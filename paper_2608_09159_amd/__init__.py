@@ -62,7 +62,8 @@ class Settings(C.Structure):
                 ("power_iters", C.c_int32), ("a_norm", C.c_double), ("omega0", C.c_double),
                 ("precision", C.c_int32), ("trace_iters", C.c_int32), ("block_dim", C.c_int32),
                 ("grid_dim", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
-                ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32)]
+                ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
+                ("time_kernels", C.c_int32)]
 
 
 class ResultC(C.Structure):
@@ -71,7 +72,8 @@ class ResultC(C.Structure):
                 ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("omega", C.c_double),
-                ("a_norm", C.c_double), ("x", _dp), ("y", _dp), ("s", _dp)]
+                ("a_norm", C.c_double), ("x", _dp), ("y", _dp), ("s", _dp),
+                ("kernel_s", C.c_double), ("kernel_launches", C.c_int64)]
 
 
 class TraceC(C.Structure):
@@ -209,7 +211,8 @@ class Handle:
                    inner_iterations=res.inner_iterations, restarts=res.restarts,
                    rel_primal=res.rel_primal, rel_dual=res.rel_dual, rel_gap=res.rel_gap,
                    primal_obj=res.primal_obj, dual_obj=res.dual_obj, setup_s=res.setup_s,
-                   solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y)
+                   solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y,
+                   kernel_s=res.kernel_s, kernel_launches=res.kernel_launches)
         if want_s:
             out["s"] = s
         return out

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -58,6 +59,8 @@ struct Instance {
   double* scratch = nullptr;   // power iteration scratch
   double qmax = 0.0;
   int grid = 1;
+  size_t bar_bytes = 0;
+  long n_warm = 0;
 };
 
 struct Handle {
@@ -181,10 +184,14 @@ int upload_instance(Handle* h, Instance* I) {
   V.gp = B.alloc<double>(n);
   V.zb = B.alloc<double>(n);
   V.s = B.alloc<double>(n);
+  V.t1 = B.alloc<double>(n);
+  V.t2 = B.alloc<double>(n);
+  I->n_warm = 2L * ((long)H.wave_start.size() + (long)H.lane_start.size());
+  V.warm = B.alloc<double>(I->n_warm);
   V.xb = V.yb = V.Axb = nullptr;
   I->scratch = B.alloc<double>(2048 + 2);
   I->ctl = B.alloc<Ctl>(1);
-  I->bar = B.alloc<Barrier>(1);
+  I->bar = nullptr;   // allocated with the grid size below
   if (h->s.trace_iters > 0) {
     long cap = h->s.trace_iters;
     I->T.cap = (int)cap;
@@ -202,12 +209,91 @@ int upload_instance(Handle* h, Instance* I) {
   int G = h->s.grid_dim;
   if (G <= 0) {
     long work = std::max<long>(std::max<long>(n, m), 1);
-    long want = (work + (long)block_size() * 4 - 1) / ((long)block_size() * 4);
+    long want = (work + (long)block_size() - 1) / (long)block_size();
     G = (int)std::min<long>(std::max<long>(want, 1), maxg);
   }
   G = std::max(1, std::min(G, maxg));
   I->grid = G;
+  // ownership ranges: coordinates weighted by their share of the A^T and P
+  // passes, the dense factor and the cone projections (cone blocks are never
+  // split); rows by their nonzeros
+  {
+    std::vector<long> pc(G + 1, 0), pr(G + 1, 0);
+    std::vector<int> pw(G + 1, 0), pl(G + 1, 0);
+    auto split = [&](const std::vector<std::pair<long, double>>& units, long total_items,
+                     std::vector<long>& out) {
+      double total = 0.0;
+      for (const auto& u : units) total += u.second;
+      out[0] = 0;
+      int kk = 1;
+      double cum = 0.0;
+      for (const auto& u : units) {
+        cum += u.second;
+        while (kk < G && cum >= total * kk / G) out[kk++] = u.first;   // u.first = end index
+      }
+      while (kk <= G) out[kk++] = total_items;
+      out[G] = total_items;
+    };
+    std::vector<std::pair<long, double>> cu;
+    cu.reserve(n);
+    for (const auto& cb : H.cones) {
+      auto wcoord = [&](long i) {
+        double w = 2.0 + (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]) + H.r;
+        if (H.P.rows > 0) w += (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
+        return w;
+      };
+      if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
+        for (long i = cb.start; i < cb.start + cb.dim; ++i) cu.emplace_back(i + 1, wcoord(i));
+      } else {
+        double w = 0.0;
+        for (long i = cb.start; i < cb.start + cb.dim; ++i) w += wcoord(i) + 16.0;
+        if (cb.type == PDHCG_CONE_EXP || cb.type == PDHCG_CONE_POW) w += 400.0;
+        cu.emplace_back((long)cb.start + cb.dim, w);
+      }
+    }
+    split(cu, n, pc);
+    std::vector<std::pair<long, double>> ru;
+    ru.reserve(m);
+    for (long l = 0; l < m; ++l) ru.emplace_back(l + 1, 2.0 + (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
+    split(ru, m, pr);
+    for (int w = 0; w <= G; ++w) {
+      pw[w] = (int)(std::lower_bound(H.wave_start.begin(), H.wave_start.end(), (int)std::min<long>(pc[w], n)) -
+                    H.wave_start.begin());
+      pl[w] = (int)(std::lower_bound(H.lane_start.begin(), H.lane_start.end(), (int)std::min<long>(pc[w], n)) -
+                    H.lane_start.begin());
+    }
+    // lanes per row chosen per workgroup from its own rows (about two
+    // nonzeros per lane), SOC/RSOC group width from its longest block
+    std::vector<unsigned char> lanes(4 * (size_t)G, 1);
+    auto pick = [](double mean) {
+      int L = 1;
+      while (L * 2 <= std::max(1.0, mean / 2.0) && L < 64) L *= 2;
+      return L;
+    };
+    for (int w = 0; w < G; ++w) {
+      long nr = pc[w + 1] - pc[w];
+      double nz = 0.0;
+      if (nr > 0) {
+        nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
+        if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
+      }
+      lanes[4 * w + 0] = (unsigned char)(h->s.lanes_at > 0 ? h->s.lanes_at : pick(nr > 0 ? nz / nr : 1.0));
+      long mr = pr[w + 1] - pr[w];
+      double mz = mr > 0 ? (double)(H.A.ptr[pr[w + 1]] - H.A.ptr[pr[w]]) / mr : 1.0;
+      lanes[4 * w + 1] = (unsigned char)(h->s.lanes_a > 0 ? h->s.lanes_a : pick(mz));
+      int maxdim = 1;
+      for (int it = pw[w]; it < pw[w + 1]; ++it) maxdim = std::max(maxdim, H.wave_dim[it]);
+      lanes[4 * w + 2] = (unsigned char)(maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64));
+    }
+    P.part_c = B.upload(pc);
+    P.part_r = B.upload(pr);
+    P.part_w = B.upload(pw);
+    P.part_l = B.upload(pl);
+    P.part_lanes = B.upload(lanes);
+  }
   V.partials = B.alloc<double>((size_t)SL_COUNT * G);
+  I->bar_bytes = sizeof(Barrier) + sizeof(unsigned) * (size_t)G * BAR_STRIDE;
+  I->bar = (Barrier*)B.alloc<char>(I->bar_bytes);
   if (B.err != hipSuccess) return PDHCG_E_MEM;
   return PDHCG_OK;
 }
@@ -397,10 +483,9 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   }
   Ctl c0;
   std::memset(&c0, 0, sizeof(c0));
-  Barrier b0;
-  std::memset(&b0, 0, sizeof(b0));
   HIPCHK(hipMemcpyAsync(I->ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(I->bar, &b0, sizeof(b0), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(I->bar, 0, I->bar_bytes, st));
+  HIPCHK(launch_fill(I->V.warm, I->n_warm, NAN, st));
   KArgs a{};
   a.P = I->P;
   a.V = I->V;
@@ -410,17 +495,78 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   a.T = I->T;
   a.spin_limit = h->spin_limit;
   a.qmax = I->qmax;
+  a.profile = h->s.verbose & 8 ? 1 : 0;
+  unsigned long long* dpt = nullptr;
+  if (a.profile) {
+    HIPCHK(hipMalloc(&dpt, sizeof(unsigned long long) * PT_COUNT * I->grid));
+    HIPCHK(hipMemsetAsync(dpt, 0, sizeof(unsigned long long) * PT_COUNT * I->grid, st));
+  }
+  a.ptimes = dpt;
   Ctl c = c0;
   int status = 0;
   const long long maxit = h->s.max_iter;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool timing = h->s.time_kernels != 0;
+  double ksum = 0.0;
+  long long nlaunch = 0;
+  if (timing) {
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+  }
   while (true) {
     a.stop_at = std::min<long long>(maxit, c.ktot + h->s.host_poll);
+    if (timing) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_solve(a, I->grid, st));
+    if (timing) HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(hipMemcpyAsync(&c, I->ctl, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ++nlaunch;
+    if (timing) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+      ksum += ms * 1e-3;
+    }
     if (c.status != 0) { status = c.status; break; }
     if (c.ktot >= maxit) { status = PDHCG_MAX_ITER; break; }
     if (now_s() - t0 > h->s.time_limit) { status = PDHCG_TIME_LIMIT; break; }
+  }
+  if (timing) {
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+  }
+  res->kernel_s = ksum;
+  res->kernel_launches = nlaunch;
+  if (h->s.verbose & 8) {
+    static const char* names[PT_COUNT] = {"init", "P1", "P2", "P3", "P4", "P6", "check",
+                                          "halpern", "barrier", "proj", "wcall", "ncall"};
+    int dev = 0, khz = 100000;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    std::vector<unsigned long long> pt((size_t)PT_COUNT * I->grid);
+    (void)hipMemcpy(pt.data(), dpt, pt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    (void)hipFree(dpt);
+    std::fprintf(stderr, "pdhcg phase times over %d workgroups (lanes at=%d a=%d): mean / max / argmax [ms]\n",
+                 I->grid, I->P.at_lanes, I->P.a_lanes);
+    for (int i = 0; i < PT_COUNT; ++i) {
+      double s = 0, mx = 0;
+      int am = 0;
+      for (int w = 0; w < I->grid; ++w) {
+        double v = pt[(size_t)w * PT_COUNT + i] / (double)khz;
+        s += v;
+        if (v > mx) { mx = v; am = w; }
+      }
+      std::fprintf(stderr, "  %-8s %10.3f %10.3f %5d\n", names[i], s / I->grid, mx, am);
+    }
+    if (const char* path = std::getenv("PDHCG_PROFILE_DUMP")) {
+      if (FILE* f = std::fopen(path, "w")) {
+        for (int w = 0; w < I->grid; ++w) {
+          std::fprintf(f, "%d,%ld,%ld", w, (long)0, (long)0);
+          for (int i = 0; i < PT_COUNT; ++i) std::fprintf(f, ",%.4f", pt[(size_t)w * PT_COUNT + i] / (double)khz);
+          std::fprintf(f, "\n");
+        }
+        std::fclose(f);
+      }
+    }
   }
   // results (unscaled)
   const double* W = I->P.q_diag ? I->V.wx : I->V.u;

@@ -57,6 +57,15 @@ struct DevProblem {
   double nu_b, nu_c, norm_b, norm_c;   // norm_b, norm_c: ||b||, ||c|| of the original data
   double eta, omega0;
   int q_diag;            // Q^ diagonal (includes Q = 0): one metric projection per prox
+  // ownership of workgroup w: coordinates [part_c[w], part_c[w+1]), rows
+  // [part_r[w], part_r[w+1]), wave items [part_w[w], ...), lane items
+  // [part_l[w], ...)
+  const long* part_c;
+  const long* part_r;
+  const int* part_w;
+  const int* part_l;
+  const unsigned char* part_lanes;  // per workgroup: lanes for A^T/P rows, A rows,
+                                    // SOC/RSOC group width, pad
 };
 
 struct DevVec {
@@ -65,6 +74,8 @@ struct DevVec {
   double *v, *u, *up, *g, *gp;   // inner-solve vectors (n)
   double *zb;                    // pre-projection buffer (n)
   double *s;                     // KKT dual slack (n)
+  double *t1, *t2;               // SpMV results of the current pass (n)
+  double *warm;                  // root-finding warm starts, 2 x (n_wave + n_lane)
   double *xb, *yb, *Axb;         // averaged scheme
   double *partials;              // SL_COUNT x G
 };
@@ -95,7 +106,12 @@ struct Ctl {
   int pad0, pad1;
   double hx[RMAX];  // R^ x of the current Halpern primal state
   double hxb[RMAX]; // R^ xbar (averaged scheme)
+  unsigned long long pt[16];  // phase timers (wall-clock ticks, workgroup 0)
 };
+
+// phase-timer categories
+enum : int { PT_INIT = 0, PT_P1, PT_P2, PT_P3, PT_P4, PT_P6, PT_CHECK, PT_HALP, PT_BAR,
+             PT_PROJ, PT_WCALL, PT_NCALL, PT_COUNT };
 
 struct TraceBufs {
   int cap;                       // 0 = off
@@ -103,11 +119,14 @@ struct TraceBufs {
   double *sc;                    // cap * 8 scalars
 };
 
+// grid barrier state: one arrival word per workgroup (64-byte stride) and a
+// release word written by workgroup 0
+constexpr int BAR_STRIDE = 16;
 struct Barrier {
-  unsigned count;
   unsigned gen;
   int abort;
-  int pad;
+  unsigned pad[BAR_STRIDE - 2];
+  unsigned arrive[1];   // really [G * BAR_STRIDE]
 };
 
 struct KArgs {
@@ -120,6 +139,8 @@ struct KArgs {
   long long stop_at;   // return to the host when ktot reaches this
   unsigned long long spin_limit;  // grid-barrier wait bound, wall-clock ticks
   double qmax;         // max_i diag(Q^)_i (first Euclidean BB step)
+  int profile;         // accumulate phase timers in ctl->pt and ptimes
+  unsigned long long* ptimes;   // [G][PT_COUNT] per-workgroup timers (profile)
 };
 
 }  // namespace pdhcg

@@ -29,16 +29,54 @@
 
 namespace pdhcg {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+#ifdef PDHCG_COUNT_ITERS
+__device__ unsigned long long pdhcg_soc_evals;
+#endif
+
+// Cross-lane reductions on DPP: quad permutations (xor 1, xor 2), row half
+// mirror (pairs lane i with 7-i), row mirror (i with 15-i), a 32-lane
+// swizzle (xor 16) and the two half-wave readlanes.  Every step adds a value
+// to its partner's with the operands merely swapped, so all lanes of a group
+// finish with bitwise identical sums and control flow that depends on them
+// stays uniform.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double swz_xor16(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over aligned groups of Lw lanes (Lw a power of two <= 64); every lane
+// of the wave must call it with the same Lw
+__device__ __forceinline__ double group_sum(double v, int Lw) {
+  if (Lw >= 2) v += dpp_d<0xB1>(v);
+  if (Lw >= 4) v += dpp_d<0x4E>(v);
+  if (Lw >= 8) v += dpp_d<0x141>(v);
+  if (Lw >= 16) v += dpp_d<0x140>(v);
+  if (Lw >= 32) v += swz_xor16(v);
+  if (Lw >= 64) v = readlane_d(v, 0) + readlane_d(v, 32);
   return v;
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  v += swz_xor16(v);
+  return readlane_d(v, 0) + readlane_d(v, 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -53,18 +91,30 @@ struct SocSol {
 };
 
 template <class In>
-__device__ SocSol soc_wave_solve(const In& in, bool euclid) {
-  const int lane = threadIdx.x & 63;
+__device__ SocSol soc_wave_solve(const In& in, bool euclid, double* warm, int Lg) {
+  const int lane = threadIdx.x & (Lg - 1);
   const double rt = in.rt(), mt = in.mt();
   const int dv = in.dimv();
-  double nv2 = 0.0, nmv2 = 0.0;
-  for (int j = lane; j < dv; j += 64) {
-    double r = in.rv(j);
-    double mr = in.mv(j) * r;
-    nv2 += r * r;
-    nmv2 += mr * mr;
+  // blocks of up to Lg + 1 coordinates keep (r_j, m_j) in one register pair per lane
+  const bool small = dv <= Lg;
+  double rr = 0.0, mm = 1.0;
+  if (small && lane < dv) {
+    rr = in.rv(lane);
+    mm = in.mv(lane);
   }
-  nv2 = wave_sum(nv2);
+  double nv2 = 0.0, nmv2 = 0.0;
+  if (small) {
+    nv2 = rr * rr;
+    nmv2 = (mm * rr) * (mm * rr);
+  } else {
+    for (int j = lane; j < dv; j += Lg) {
+      double r = in.rv(j);
+      double mr = in.mv(j) * r;
+      nv2 += r * r;
+      nmv2 += mr * mr;
+    }
+  }
+  nv2 = group_sum(nv2, Lg);
   const double a = sqrt(nv2);
   SocSol out{0, 0.0, 0.0, 0.0};
   if (a <= rt) return out;
@@ -75,60 +125,88 @@ __device__ SocSol soc_wave_solve(const In& in, bool euclid) {
     out.tval = 0.5 * (a + rt);
     return out;
   }
-  nmv2 = wave_sum(nmv2);
+  nmv2 = group_sum(nmv2, Lg);
   if (sqrt(nmv2) <= -mt * rt) { out.kind = 1; return out; }
   out.kind = 3;
   if (rt == 0.0) {                      // singular case lam = m_t
     double s2 = 0.0;
-    for (int j = lane; j < dv; j += 64) {
-      double m = in.mv(j);
-      double vj = m * in.rv(j) / (m + mt);
-      s2 += vj * vj;
+    if (small) {
+      const double vj = mm * rr / (mm + mt);
+      s2 = vj * vj;
+    } else {
+      for (int j = lane; j < dv; j += Lg) {
+        double m = in.mv(j);
+        double vj = m * in.rv(j) / (m + mt);
+        s2 += vj * vj;
+      }
     }
     out.lam = mt;
-    out.tval = sqrt(wave_sum(s2));
+    out.tval = sqrt(group_sum(s2, Lg));
     return out;
   }
   const double sg = rt > 0.0 ? 1.0 : -1.0;
   const double art = fabs(rt);
   auto eval = [&](double d, double& psi, double& dpsi) {
+#ifdef PDHCG_COUNT_ITERS
+    if (lane == 0 && blockIdx.x == 0) atomicAdd(&pdhcg_soc_evals, 1ull);
+#endif
     double s2 = 0.0, s3 = 0.0;
     const double base = mt - sg * d;
-    for (int j = lane; j < dv; j += 64) {
-      double m = in.mv(j);
-      double den = m + base;
-      double vj = m * in.rv(j) / den;
-      s2 += vj * vj;
-      s3 += vj * vj / den;
+    if (small) {
+      const double inv = 1.0 / (mm + base);
+      const double vj = mm * rr * inv;
+      s2 = vj * vj;
+      s3 = s2 * inv;
+    } else {
+      for (int j = lane; j < dv; j += Lg) {
+        double m = in.mv(j);
+        const double inv = 1.0 / (m + base);
+        double vj = m * in.rv(j) * inv;
+        s2 += vj * vj;
+        s3 += vj * vj * inv;
+      }
     }
-    s2 = wave_sum(s2);
-    s3 = wave_sum(s3);
+    s2 = group_sum(s2, Lg);
+    s3 = group_sum(s3, Lg);
     double nv = sqrt(s2);
     psi = d * nv - mt * art;
     dpsi = nv + (nv > 0.0 ? d * sg * s3 / nv : 0.0);
   };
-  double lo = 0.0, hi = mt, psi, dpsi;
-  if (sg < 0.0) {
-    for (int it = 0; it < 2100; ++it) {
-      eval(hi, psi, dpsi);
-      if (psi > 0.0) break;
-      lo = hi;
-      hi *= 2.0;
-    }
+  // psi is increasing; for r_t > 0 it is convex on (0, m_t), for r_t < 0
+  // concave on (0, inf).  Newton from either side therefore overshoots at most
+  // once (to the right of the root for r_t > 0, where hi = m_t bounds it; to
+  // the left for r_t < 0, where lo bounds it) and needs no upper bracket for
+  // r_t < 0.  Steps leaving the bracket fall back to bisection / doubling.
+  double lo = 0.0, hi = sg > 0.0 ? mt : INFINITY, psi, dpsi;
+  // start: the previous root of this block, else the Euclidean estimate
+  // t = (||r_v|| + r_t)/2 (t = m_t |r_t| / delta), else the middle
+  double d = sg > 0.0 ? 0.5 * mt : mt;
+  {
+    const double w0 = warm ? *warm : NAN;
+    const double tE = 0.5 * (a + rt);
+    if (w0 > lo && w0 < hi) d = w0;
+    else if (tE > 0.0 && mt * art / tE > lo && mt * art / tE < hi) d = mt * art / tE;
   }
-  double d = 0.5 * (lo + hi);
-  for (int it = 0; it < 300; ++it) {
+  for (int it = 0; it < 400; ++it) {
     eval(d, psi, dpsi);
     if (psi < 0.0) lo = d; else hi = d;
     if (psi == 0.0) break;
     double dn = d - psi / dpsi;
-    if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
-    if (fabs(dn - d) <= 4.0 * 2.220446049250313e-16 * d || hi - lo <= 4.0 * 2.220446049250313e-16 * hi) {
+    // converged: the Newton correction is below the resolution of d (tested
+    // before the bracket test, since a converged step may land on the
+    // bracket end it has just set)
+    if (fabs(dn - d) <= 4.0 * 2.220446049250313e-16 * d) {
+      d = dn;
+      break;
+    }
+    if (!(dn > lo && dn < hi)) dn = isfinite(hi) ? 0.5 * (lo + hi) : 2.0 * fmax(d, lo);
+    if (isfinite(hi) && hi - lo <= 4.0 * 2.220446049250313e-16 * hi) {
       d = dn;
       break;
     }
     d = dn;
   }
+  if (warm && lane == 0) *warm = d;
   out.lam = mt - sg * d;
   out.tval = mt * art / d;
   return out;
@@ -172,17 +250,21 @@ struct RsocView {
   __device__ double mt() const { return 1.0; }
 };
 
-// Project block [0, dim) of Src onto SOC (type 2) or RSOC (type 3); the
-// result for local coordinate j is delivered to sink(j, value).  Every lane
-// of the wave must call this with identical arguments.
+// Project block [0, dim) of Src onto SOC (type 2) or RSOC (type 3) with an
+// aligned group of Lg lanes (16, 32 or 64); the result for local coordinate j
+// is delivered to sink(j, value).  Every lane of the group must call this
+// with identical arguments; other groups of the wave may work on other
+// blocks (all reductions stay inside the group).  warm (nullable)
+// holds the previous root of this block and receives the new one.
 template <class Src, class Sink>
-__device__ void project_wave_item(int type, int dim, bool euclid, const Src& src, Sink sink) {
-  const int lane = threadIdx.x & 63;
+__device__ __noinline__ void project_wave_item(int type, int dim, bool euclid, const Src& src, Sink sink,
+                                               double* warm, int Lg) {
+  const int lane = threadIdx.x & (Lg - 1);
   if (type == 2) {
     SocView<Src> view{src, dim};
-    SocSol s = soc_wave_solve(view, euclid);
-    for (int j = lane; j < dim - 1; j += 64) sink(j, soc_out_v(s, src.r(j), src.m(j)));
-    if (lane == ((dim - 1) & 63)) sink(dim - 1, soc_out_t(s, src.r(dim - 1)));
+    SocSol s = soc_wave_solve(view, euclid, warm, Lg);
+    for (int j = lane; j < dim - 1; j += Lg) sink(j, soc_out_v(s, src.r(j), src.m(j)));
+    if (lane == ((dim - 1) & (Lg - 1))) sink(dim - 1, soc_out_t(s, src.r(dim - 1)));
     return;
   }
   // RSOC
@@ -193,8 +275,8 @@ __device__ void project_wave_item(int type, int dim, bool euclid, const Src& src
   const double q = sms * smt;
   const double h = 0.70710678118654752440;
   RsocView<Src> view{src, dim, q, sqrt(q), (sms * rs - smt * rtt) * h, (sms * rs + smt * rtt) * h};
-  SocSol s = soc_wave_solve(view, euclid);
-  for (int j = lane; j < dim - 2; j += 64) {
+  SocSol s = soc_wave_solve(view, euclid, warm, Lg);
+  for (int j = lane; j < dim - 2; j += Lg) {
     double vp = soc_out_v(s, view.rv(j), view.mv(j));
     sink(j, s.kind == 0 ? src.r(j) : vp / view.sq);
   }
@@ -295,18 +377,56 @@ __device__ __forceinline__ double exp_N(const ExpData& e, double rho) {
 
 constexpr double RHO_LIM = 1.0e100;
 
-// f(kind, rho): 0 -> H, 1 -> vis, 2 -> N
+// H and dH/drho (both divided by e^{2 rho} for rho > 0)
+__device__ __forceinline__ void exp_H_d(const ExpData& e, double rho, double& H, double& dH) {
+  const double A = e.mr * e.r0 * (rho - 1.0) + e.ms * e.s0;
+  const double B = e.mr * rho * (rho - 1.0) + e.ms;
+  const double Cc = rho * e.s0 - e.r0;
+  const double dB = e.mr * (2.0 * rho - 1.0);
+  if (rho > 0.0) {
+    const double em = exp(-rho), em2 = em * em;
+    H = e.mt * A - e.mt * e.t0 * em * B + e.mr * e.ms * Cc * em2;
+    dH = e.mt * e.mr * e.r0 - e.mt * e.t0 * em * (dB - B) + e.mr * e.ms * em2 * (e.s0 - 2.0 * Cc);
+  } else {
+    const double x = exp(rho), x2 = x * x;
+    H = e.mt * x2 * A - e.mt * e.t0 * x * B + e.mr * e.ms * Cc;
+    dH = e.mt * x2 * (2.0 * A + e.mr * e.r0) - e.mt * e.t0 * x * (B + dB) + e.mr * e.ms * e.s0;
+  }
+}
+
+// f(kind, rho) and its derivative: 0 -> H (scaled), 1 -> vis, 2 -> N
 __device__ __forceinline__ double exp_f(const ExpData& e, int kind, double rho) {
   return kind == 0 ? exp_H(e, rho) : (kind == 1 ? exp_vis(e, rho) : exp_N(e, rho));
 }
 
-// bisection for a sign change of f on [lo, hi]; `inc` means negative at lo
+__device__ __forceinline__ double exp_df(const ExpData& e, int kind, double rho) {
+  if (kind == 0) {
+    double H, dH;
+    exp_H_d(e, rho, H, dH);
+    return dH;
+  }
+  if (rho > 700.0) return NAN;
+  const double x = exp(rho);
+  return kind == 1 ? x * (e.r0 - rho * e.s0) : e.mr * e.r0 + e.mt * e.t0 * x;
+}
+
+// sign change of f on [lo, hi] (`inc`: negative at lo): Newton steps inside
+// the bracket, bisection when a step leaves it or stalls
 __device__ double exp_bisect(const ExpData& e, int kind, double lo, double hi, bool inc) {
+  double x = 0.5 * (lo + hi);
+  double prev = INFINITY;
   for (int it = 0; it < 3000; ++it) {
-    double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi || hi - lo <= 8.881784197001252e-16 * fmax(1.0, fabs(mid))) break;
-    double v = exp_f(e, kind, mid);
-    if ((v < 0.0) == inc) lo = mid; else hi = mid;
+    if (!(lo < hi) || hi - lo <= 8.881784197001252e-16 * fmax(1.0, fabs(x))) break;
+    const double v = exp_f(e, kind, x);
+    if (v == 0.0) return x;
+    if ((v < 0.0) == inc) lo = x; else hi = x;
+    const double dv = exp_df(e, kind, x);
+    double xn = (isfinite(dv) && dv != 0.0) ? x - v / dv : NAN;
+    if (fabs(xn - x) <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(x))) return xn;   // converged
+    const double mid = 0.5 * (lo + hi);
+    if (!(xn > lo && xn < hi) || fabs(xn - x) > 0.5 * prev) xn = mid;
+    prev = fabs(xn - x);
+    x = xn;
   }
   return 0.5 * (lo + hi);
 }
@@ -405,12 +525,50 @@ __device__ int exp_positive(const ExpData& e, Ival out[2]) {
   return 2;
 }
 
+// Newton on H from rho0.  A root at which eta_M > 0 (N > 0) and the ray is
+// visible from r (psi > t0) is the projection (the normal M(r - u) then
+// points outward, so u satisfies the projection's optimality conditions);
+// anything else is rejected and the caller falls back to the bracket search.
+__device__ bool exp_newton(const ExpData& e, double rho, double out[3], double* warm) {
+  for (int it = 0; it < 60; ++it) {
+    double H, dH;
+    exp_H_d(e, rho, H, dH);
+    if (!(dH != 0.0) || !isfinite(H) || !isfinite(dH)) return false;
+    double step = H / dH;
+    const double cap = fmax(2.0, 0.5 * fabs(rho));
+    if (step > cap) step = cap;
+    if (step < -cap) step = -cap;
+    const double rn = rho - step;
+    if (fabs(rn - rho) <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(rho))) {
+      rho = rn;
+      if (!(exp_N(e, rho) > 0.0) || !(exp_vis(e, rho) > 0.0)) return false;
+      exp_point(e, rho, out);
+      if (!(out[1] >= 0.0 && isfinite(out[0]) && isfinite(out[2]))) return false;
+      if (warm) *warm = rho;
+      return true;
+    }
+    rho = rn;
+    if (fabs(rho) > 700.0) return false;
+  }
+  return false;
+}
+
 __device__ __noinline__ void project_exp(double r0, double s0, double t0, double mr, double ms, double mt,
-                            double out[3]) {
+                            double out[3], double* warm) {
   if (exp_in_cone(r0, s0, t0)) { out[0] = r0; out[1] = s0; out[2] = t0; return; }
   if (exp_in_dual(-mr * r0, -ms * s0, -mt * t0)) { out[0] = out[1] = out[2] = 0.0; return; }
   if (r0 <= 0.0 && s0 <= 0.0) { out[0] = r0; out[1] = 0.0; out[2] = fmax(t0, 0.0); return; }
   ExpData e{r0, s0, t0, mr, ms, mt};
+  {
+    // start: the previous root of this block, else the ratio of r itself when
+    // s0 > 0, else the boundary ratio log(t0 / r0) of the t-r face
+    double rho0 = 0.0;
+    if (s0 > 0.0) rho0 = fmin(fmax(r0 / s0, -50.0), 50.0);
+    else if (t0 > 0.0 && r0 > 0.0) rho0 = fmin(fmax(log(t0 / r0), -50.0), 50.0);
+    double rho_w = warm ? *warm : NAN;
+    if (isfinite(rho_w) && exp_newton(e, rho_w, out, warm)) return;
+    if (exp_newton(e, rho0, out, warm)) return;
+  }
   Ival V[2], Np[2];
   int nv = exp_visible(e, V);
   int nn = exp_positive(e, Np);
@@ -438,7 +596,10 @@ __device__ __noinline__ void project_exp(double r0, double s0, double t0, double
       }
       double rho = exp_bisect(e, 0, lo, hi, true);
       exp_point(e, rho, out);
-      if (out[1] >= 0.0) return;
+      if (out[1] >= 0.0) {
+        if (warm) *warm = rho;
+        return;
+      }
     }
   if (!isnan(fallback)) {
     exp_point(e, fallback, out);
@@ -456,7 +617,7 @@ __device__ __forceinline__ double pow_qroot(double s, double c) {
 }
 
 __device__ __noinline__ void project_pow(double x, double y, double z, double al, double mx, double my,
-                            double mz, double out[3]) {
+                            double mz, double out[3], double* warm) {
   if (z == 0.0) { out[0] = fmax(x, 0.0); out[1] = fmax(y, 0.0); out[2] = 0.0; return; }
   if (x >= 0.0 && y >= 0.0 && pow(x, al) * pow(y, 1.0 - al) >= fabs(z)) {
     out[0] = x; out[1] = y; out[2] = z; return;
@@ -470,18 +631,33 @@ __device__ __noinline__ void project_pow(double x, double y, double z, double al
   }
   const double R = fabs(z);
   const double cx = al * mz / mx, cy = (1.0 - al) * mz / my;
+  // g_M is positive left of its unique root in (0, R) and negative right of
+  // it; Newton steps are taken inside the sign bracket, bisection otherwise.
   double lo = 0.0, hi = R;
   const double tol = 1e-15 * fmax(1.0, R);
+  double rho = 0.5 * R;
+  if (warm && *warm > 0.0 && *warm < R) rho = *warm;
   for (int it = 0; it < 3000 && hi - lo > tol; ++it) {
-    double mid = 0.5 * (lo + hi);
-    double w = mid * (R - mid);
-    double xv = pow_qroot(x, cx * w), yv = pow_qroot(y, cy * w);
-    double g = (xv > 0.0 && yv > 0.0) ? al * log(xv) + (1.0 - al) * log(yv) - log(mid) : -INFINITY;
-    if (g > 0.0) lo = mid;
-    else if (g < 0.0) hi = mid;
-    else { lo = hi = mid; break; }
+    const double w = rho * (R - rho), dw = R - 2.0 * rho;
+    const double xv = pow_qroot(x, cx * w), yv = pow_qroot(y, cy * w);
+    double g, dg = 0.0;
+    if (xv > 0.0 && yv > 0.0) {
+      g = al * log(xv) + (1.0 - al) * log(yv) - log(rho);
+      const double dx = cx * dw / (2.0 * xv - x), dy = cy * dw / (2.0 * yv - y);
+      dg = al * dx / xv + (1.0 - al) * dy / yv - 1.0 / rho;
+    } else {
+      g = -INFINITY;
+    }
+    if (g > 0.0) lo = rho;
+    else if (g < 0.0) hi = rho;
+    else { lo = hi = rho; break; }
+    double rn = (isfinite(g) && dg < 0.0) ? rho - g / dg : 0.5 * (lo + hi);
+    if (fabs(rn - rho) <= 2.220446049250313e-16 * rho) { lo = hi = rn; break; }   // converged
+    if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+    rho = rn;
   }
-  const double rho = 0.5 * (lo + hi);
+  rho = 0.5 * (lo + hi);
+  if (warm) *warm = rho;
   const double w = rho * (R - rho);
   out[0] = pow_qroot(x, cx * w);
   out[1] = pow_qroot(y, cy * w);

@@ -1,30 +1,33 @@
-// Persistent cooperative solver kernel for restarted PDHG on conic QP.
+// Persistent solver kernels for restarted PDHG on conic QP.
 //
-// One launch runs outer iterations until the next host poll point, the
-// iteration limit or termination.  The workgroups of the grid form one team:
-// phases are separated by a grid barrier, every reduction is written as one
-// partial per workgroup and re-reduced by every workgroup in the same fixed
-// order (deterministic and identical everywhere), so every workgroup takes
-// the same control decisions (inner stop, restart, termination) without any
-// host round trip.
+// Work decomposition: a "team" of workgroups solves one problem.  Each
+// workgroup owns a contiguous range of coordinates (never splitting a cone
+// block) and a contiguous range of rows of A, balanced by work on the host,
+// so every per-coordinate step -- prox, cone projections, Halpern update --
+// is local to the workgroup and needs only __syncthreads.  Grid barriers
+// remain only where a global reduction or a gather over all coordinates is
+// needed.  Every reduction is written as one partial per workgroup and
+// re-reduced by every workgroup in the same fixed order (deterministic and
+// identical everywhere), so all workgroups take the same control decisions
+// (inner stop, restart, termination) without a host round trip.
 //
 // Outer iteration (reflected-Halpern epoch, eq. stored-pdhg-candidate and
 // eq. rh-update; primal-first PDHG operator eq. theory-pdhg-map):
-//   P1  coordinate pass over rows of A^T:  v = x + tau A^T y; diagonal Q:
-//       x~ = (v - tau c)/(1 + tau q) (eq. diagonal-q-metric), elementwise
-//       cones projected at once; general Q: g0 = Q x + c + (x - v)/tau and the
-//       first Jacobi step (alpha = 1).
-//   P2  cone blocks projected in the metric (wave per SOC/RSOC, lane per
-//       EXP/POW).
-//   P3/P4 repeated: g = Q u + c + (u - v)/tau, BB step length
-//       <s, J s>/<s, dg> (eq. jacobi-bb-step), projected step; stop when the
-//       Euclidean step norm <= eps_in (eq. current-inner-step-stop).
-//   P6  row pass over A: A w_x, w_y = y + sigma (b - (2 A w_x - A x)); on
-//       non-check iterations the Halpern update of x, y and A x is fused here.
+//   P1  own coordinates: A^T y (SpMV rows of A^T), v = x + tau A^T y.
+//       Diagonal Q: x~ = (v - tau c)/(1 + tau q) (eq. diagonal-q-metric)
+//       projected at once (elementwise cones, then own cone blocks in the
+//       metric 1 + tau q).  General Q: g0 = Q x + c + (x - v)/tau and the first
+//       Jacobi step with alpha = 1 (eq. jacobi-bb-step).             | barrier
+//   P3  (general Q, repeated) g = Q u + c + (u - v)/tau, BB sums.    | barrier
+//   P4  projected step with alpha = <s,Js>/<s,dg>; stop when the Euclidean
+//       step norm <= eps_in (eq. current-inner-step-stop).           | barrier
+//   P6  own rows: A w_x, w_y = y + sigma (b - (2 A w_x - A x)); on non-check
+//       iterations the Halpern update of x, y, A x is fused.          | barrier
 //   Check iterations (k = 0 of an epoch and every check_every evaluations):
-//       fixed-point error E (eq. practical-fixed-point-movement), restart rule
-//       (eq. practical-restart-rule), relative KKT residuals of the unscaled
-//       candidate, PID primal weight on restart (eq. pid-error, pid-weight).
+//       fixed-point error E (eq. practical-fixed-point-movement), relative KKT
+//       residuals of the unscaled candidate (one A^T pass + Euclidean cone
+//       projections of -s), restart rule (eq. practical-restart-rule), PID
+//       primal weight (eq. pid-error, pid-weight), then restart or Halpern.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -35,9 +38,8 @@
 
 namespace pdhcg {
 
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 512;
 constexpr int NWAVE = BLOCK / 64;
-constexpr double DEPS = 2.220446049250313e-16;
 
 struct Lds {
   double red[16][NWAVE];
@@ -46,51 +48,107 @@ struct Lds {
   double ht[RMAX];       // D^ h for the Q product of the current pass
   double hu[RMAX];       // R^ u of the current inner iterate
   Ctl C;
-  double tau, sigma, alpha, last;
   int flag;
   int done;
+  int pcat;
+  unsigned long long plast;
+  unsigned epoch;
+  unsigned long long pt[PT_COUNT];   // this workgroup's phase timers
 };
 
+// phase timer: charge the time since the last mark to the current category
+// and switch to `cat` (thread 0 of the timing workgroup only)
+__device__ __forceinline__ void tmark(Lds& L, bool on, int cat) {
+  if (on && threadIdx.x == 0) {
+    const unsigned long long t = wall_clock64();
+    L.pt[L.pcat] += t - L.plast;
+    L.plast = t;
+    L.pcat = cat;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// grid barrier with a bounded wait: if a workgroup waits longer than
-// `limit` ticks of the constant-rate wall clock, the abort flag is raised and
-// every workgroup leaves the kernel at its next barrier.
+// grid barrier.  Every workgroup writes back its L2 (agent-scope release
+// fence) and stores the barrier epoch in its own arrival word; workgroup 0
+// polls all arrival words and then publishes the epoch in the release word;
+// everyone else polls the release word and invalidates its L2 (agent-scope
+// acquire fence).  No atomic read-modify-write, one fence pair per
+// workgroup.  Waits are bounded: after `limit` ticks of the constant-rate
+// wall clock the abort flag is raised and every workgroup leaves the kernel
+// at its next barrier.
 // ---------------------------------------------------------------------------
 __device__ bool grid_sync(Barrier* bar, int G, Lds& L, unsigned long long limit) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int ab = 0;
-    __threadfence();
-    if (G > 1) {
-      unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == (unsigned)G - 1u) {
-        __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&bar->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          __builtin_amdgcn_s_sleep(1);
-          if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-          if (wall_clock64() - t0 > limit) {
-            __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-        }
+  if (G == 1) return true;
+  const int tid = threadIdx.x;
+  if (tid == 0) L.epoch += 1u;
+  __syncthreads();
+  const unsigned ep = L.epoch;
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&bar->arrive[blockIdx.x * BAR_STRIDE], ep, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    L.flag = 0;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < 64) {
+      const unsigned long long t0 = wall_clock64();
+      int bad = 0;
+      while (true) {
+        int pending = 0;
+        for (int j = tid; j < G; j += 64)
+          pending |= (__hip_atomic_load(&bar->arrive[j * BAR_STRIDE], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) != ep);
+        if (__ballot(pending) == 0ull) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > limit) { bad = 1; break; }
       }
-      __threadfence();
-      ab = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        if (bad) __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(&bar->gen, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        L.flag = bad;
+      }
     }
-    L.flag = ab;
+  } else if (tid == 0) {
+    const unsigned long long t0 = wall_clock64();
+    int bad = 0;
+    while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad = 1;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    L.flag = bad;
   }
   __syncthreads();
   return L.flag == 0;
 }
 
-// sum of up to 16 per-thread values over the workgroup; thread 0..k-1 store
-// partial[slot * G + rank]
+struct GridTeam {
+  Barrier* bar;
+  unsigned long long limit;
+  int rank, size;
+  __device__ bool sync(Lds& L) const { return grid_sync(bar, size, L, limit); }
+};
+
+struct SoloTeam {
+  int rank = 0, size = 1;
+  __device__ bool sync(Lds&) const {
+    __syncthreads();
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// workgroup reductions into per-workgroup partials
+// ---------------------------------------------------------------------------
+// sum of up to 16 per-thread values over the workgroup; partial[slot * G + rank]
 __device__ void block_store(Lds& L, const double* v, const int* slots, int k, double* partials,
                             int G, int rank) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -107,14 +165,13 @@ __device__ void block_store(Lds& L, const double* v, const int* slots, int k, do
   __syncthreads();
 }
 
-// R^ u accumulators (one row of partials per rank of R)
-__device__ __forceinline__ void hw_clear(Lds& L, int r) {
+__device__ __forceinline__ void hw_clear(Lds& L) {
   for (int i = threadIdx.x; i < NWAVE * RMAX; i += BLOCK) (&L.hw[0][0])[i] = 0.0;
   __syncthreads();
 }
 
-// wave-uniform: add R[k, i] * val for this lane (0 if !active)
-__device__ __forceinline__ void hw_add(Lds& L, const double* R, int n, int r, long i, double val,
+// wave-uniform: add R[k, i] * val (0 if !active) to the wave's accumulators
+__device__ __forceinline__ void hw_add(Lds& L, const double* R, long n, int r, long i, double val,
                                        bool active) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = 0; k < r; ++k) {
@@ -134,7 +191,7 @@ __device__ void hw_store(Lds& L, int r, double* partials, int G, int rank) {
   __syncthreads();
 }
 
-// reduce `k` slots over the G partials into L.scal[slot]; waves share slots
+// reduce `k` slots over the G partials into L.scal[slot]
 __device__ void team_reduce(Lds& L, const double* partials, int G, const int* slots, int k) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = wv; i < k; i += NWAVE) {
@@ -161,6 +218,7 @@ __device__ void team_reduce_h(Lds& L, const double* partials, int G, int r, doub
 
 // L.ht = D h
 __device__ void make_ht(Lds& L, const DevProblem& P, const double* h) {
+  __syncthreads();
   if ((int)threadIdx.x < P.r) {
     double s = 0.0;
     for (int b = 0; b < P.r; ++b) s += P.Dm[threadIdx.x * P.r + b] * h[b];
@@ -169,19 +227,50 @@ __device__ void make_ht(Lds& L, const DevProblem& P, const double* h) {
   __syncthreads();
 }
 
-__device__ __forceinline__ double group_sum(double v, int Lw) {
-  for (int o = Lw >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 __device__ __forceinline__ double spmv_row(const int64_t* ptr, const int* col, const double* val,
                                            const double* x, long row, int sub, int Lw, bool active) {
   double acc = 0.0;
   if (active) {
     const int64_t e = ptr[row + 1];
+#pragma unroll 4
     for (int64_t k = ptr[row] + sub; k < e; k += Lw) acc += val[k] * x[col[k]];
   }
   return group_sum(acc, Lw);
+}
+
+// rows [r0, r1) of a CSR matrix times x into out, Lw lanes per row, this
+// workgroup only
+__device__ void spmv_range(const int64_t* ptr, const int* col, const double* val, const double* x,
+                           double* out, long r0, long r1, int Lw) {
+  const int groups = BLOCK / Lw;
+  const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
+  for (long base = r0; base < r1; base += groups) {
+    const long row = base + gid;
+    const bool act = row < r1;
+    const double s = spmv_row(ptr, col, val, x, row, sub, Lw, act);
+    if (act && sub == 0) out[row] = s;
+  }
+}
+
+// wave-uniform loop over the coordinates [c0, c1): f(i, active)
+template <class F>
+__device__ __forceinline__ void for_range(long c0, long c1, F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (long base = c0 + (long)wv * 64; base < c1; base += BLOCK) {
+    const long i = base + lane;
+    f(i, i < c1);
+  }
+}
+
+// rows [r0, r1) with Lw lanes per row: f(row, sub, active) (wave-uniform)
+template <class F>
+__device__ __forceinline__ void for_rows_range(long r0, long r1, int Lw, F f) {
+  const int groups = BLOCK / Lw;
+  const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
+  for (long base = r0; base < r1; base += groups) {
+    const long row = base + gid;
+    f(row, sub, row < r1);
+  }
 }
 
 __device__ __forceinline__ double elem_proj(uint8_t ct, double z) {
@@ -223,139 +312,151 @@ struct StepSrc {            // u - alpha g / d
   __device__ double m(int j) const { return M(st + j); }
 };
 
-// project every SOC/RSOC (wave items) and EXP/POW (lane items) block of src
-// into dst.  After it returns, dst holds the projected cone coordinates of
-// the blocks this wave processed and the block-scope fence makes them
-// visible to the whole workgroup.
+// this workgroup's cone items: wave items [w0, w1) (SOC/RSOC blocks), one
+// per aligned group of lg lanes (lg = 16, 32 or 64, so 4, 2 or 1 blocks per
+// wave); lane items [l0, l1) (EXP/POW blocks) spread over the waves (item k
+// of the workgroup goes to wave k % NWAVE)
+struct Items {
+  int w0, w1, l0, l1, lg;
+};
+
+// warm (nullable): previous roots of the root-finding projections, one per
+// item (wave items first, then lane items), read as starting points and
+// overwritten with the new roots
 template <class MakeSrc>
-__device__ void project_cone_items(const DevProblem& P, int gw, int gwaves, bool force_euclid,
-                                   MakeSrc make, double* dst) {
-  const int lane = threadIdx.x & 63;
-  for (int it = gw; it < P.n_wave; it += gwaves) {
+__device__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
+                              double* dst, double* warm, unsigned long long* ptw = nullptr) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gpw = 64 / I.lg;                       // groups per wave
+  for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
     const long st = P.wave_start[it];
-    const int dim = P.wave_dim[it];
     auto src = make(st);
     const bool eu = force_euclid || P.wave_euclid[it];
-    project_wave_item(P.wave_type[it], dim, eu, src, [&](int j, double v) { dst[st + j] = v; });
+    const unsigned long long t0 = ptw ? wall_clock64() : 0ull;
+    project_wave_item(P.wave_type[it], P.wave_dim[it], eu, src,
+                      [&](int j, double v) { dst[st + j] = v; }, warm ? warm + it : nullptr, I.lg);
+    if (ptw && threadIdx.x == 0) {
+      ptw[0] += wall_clock64() - t0;
+      ptw[1] += 1;
+    }
   }
-  for (long base = (long)gw * 64; base < P.n_lane; base += (long)gwaves * 64) {
-    const long it = base + lane;
-    if (it < P.n_lane) {
+  for (int kb = 0; I.l0 + kb < I.l1; kb += BLOCK) {
+    const int it = I.l0 + kb + wv + NWAVE * lane;
+    if (it < I.l1) {
       const long st = P.lane_start[it];
       auto src = make(st);
       const bool eu = force_euclid || P.lane_euclid[it];
-      double r0 = src.r(0), r1 = src.r(1), r2 = src.r(2);
+      const double r0 = src.r(0), r1 = src.r(1), r2 = src.r(2);
       double m0 = 1.0, m1 = 1.0, m2 = 1.0;
       if (!eu) { m0 = src.m(0); m1 = src.m(1); m2 = src.m(2); }
       double o[3];
-      if (P.lane_type[it] == PDHCG_CONE_EXP) project_exp(r0, r1, r2, m0, m1, m2, o);
-      else project_pow(r0, r1, r2, P.lane_alpha[it], m0, m1, m2, o);
+      double* w = warm ? warm + P.n_wave + it : nullptr;
+      if (P.lane_type[it] == PDHCG_CONE_EXP) project_exp(r0, r1, r2, m0, m1, m2, o, w);
+      else project_pow(r0, r1, r2, P.lane_alpha[it], m0, m1, m2, o, w);
       dst[st] = o[0];
       dst[st + 1] = o[1];
       dst[st + 2] = o[2];
     }
   }
-  __threadfence_block();
+  __syncthreads();
 }
 
-// wave-uniform iteration over the coordinates of every cone item of this wave:
-// f(i, active) with i a global coordinate
+// wave-uniform iteration over the coordinates of this workgroup's cone items
+// (same item-to-group mapping as project_items)
 template <class F>
-__device__ void for_cone_coords(const DevProblem& P, int gw, int gwaves, F f) {
-  const int lane = threadIdx.x & 63;
-  for (int it = gw; it < P.n_wave; it += gwaves) {
-    const long st = P.wave_start[it];
-    const int dim = P.wave_dim[it];
-    for (int jb = 0; jb < dim; jb += 64) {
-      const int j = jb + lane;
-      f(st + j, j < dim);
+__device__ void for_item_coords(const DevProblem& P, const Items& I, F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gpw = 64 / I.lg;
+  const int gl = lane & (I.lg - 1);
+  for (int base = I.w0 + wv * gpw; base < I.w1; base += NWAVE * gpw) {
+    const int it = base + lane / I.lg;
+    const bool ok = it < I.w1;
+    const long st = ok ? P.wave_start[it] : 0;
+    const int dim = ok ? P.wave_dim[it] : 0;
+    int maxd = dim;                                  // longest block of the wave
+    for (int o = 32; o >= 1; o >>= 1) maxd = max(maxd, __shfl_xor(maxd, o, 64));
+    for (int jb = 0; jb < maxd; jb += I.lg) {
+      const int j = jb + gl;
+      f(st + j, ok && j < dim);
     }
   }
-  for (long base = (long)gw * 64; base < P.n_lane; base += (long)gwaves * 64) {
-    const long it = base + lane;
-    const bool act = it < P.n_lane;
+  for (int kb = 0; I.l0 + kb < I.l1; kb += BLOCK) {
+    const int it = I.l0 + kb + wv + NWAVE * lane;
+    const bool act = it < I.l1;
     const long st = act ? P.lane_start[it] : 0;
     for (int j = 0; j < 3; ++j) f(st + j, act);
   }
 }
 
-// wave-uniform iteration over elementwise coordinates
-template <class F>
-__device__ void for_elem_coords(const DevProblem& P, int gw, int gwaves, F f) {
-  const int lane = threadIdx.x & 63;
-  for (long base = (long)gw * 64; base < P.n; base += (long)gwaves * 64) {
-    const long i = base + lane;
-    const bool act = i < P.n && P.ctype[i] != CT_CONE;
-    f(i, act);
-  }
-}
-
-// wave-uniform iteration over rows with Lw lanes per row
-template <class F>
-__device__ void for_rows(long nrows, int Lw, int gw, int gwaves, F f) {
-  const int lane = threadIdx.x & 63;
-  const int per = 64 / Lw;
-  for (long base = (long)gw * per; base < nrows; base += (long)gwaves * per) {
-    const long row = base + lane / Lw;
-    f(row, lane & (Lw - 1), row < nrows);
-  }
-}
-
 // ---------------------------------------------------------------------------
-// the kernel
+// the solver core, shared by the single-problem grid kernel and the batch
+// kernel
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
-  __shared__ Lds L;
-  const DevProblem& P = A.P;
-  const DevVec& V = A.V;
-  const DevSettings& S = A.S;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int rank = blockIdx.x, G = gridDim.x;
-  const int gw = rank * NWAVE + wv, gwaves = G * NWAVE;
+struct Own {
+  long c0, c1, r0, r1;
+  Items it;
+  int la, lr;   // lanes per row of A^T / P (own coordinates) and of A (own rows)
+};
+
+template <class Team>
+__device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V, Ctl* ctl,
+                           const Team& T, Lds& L, const Own& own, bool prof) {
+  const int tid = threadIdx.x;
+  const int rank = T.rank, G = T.size;
   const long n = P.n, m = P.m;
   const int r = P.r;
-  const unsigned long long lim = A.spin_limit;
+  const DevSettings& S = A.S;
   double* part = V.partials;
-
-  if (tid == 0) L.C = *A.ctl;
-  __syncthreads();
-  if (L.C.status != 0) return;
+  const long c0 = own.c0, c1 = own.c1, r0 = own.r0, r1 = own.r1;
+  const Items& IT = own.it;
+  const bool has_items = (IT.w1 > IT.w0) || (IT.l1 > IT.l0);
 
 #define SYNC_OR_EXIT()                         \
   do {                                         \
-    if (!grid_sync(A.bar, G, L, lim)) {        \
+    const int _cat = L.pcat;                   \
+    tmark(L, prof, PT_BAR);                    \
+    const bool _ok = T.sync(L);                \
+    tmark(L, prof, _cat);                      \
+    if (!_ok) {                                \
       if (rank == 0 && tid == 0) {             \
         L.C.status = PDHCG_ABORTED;            \
-        *A.ctl = L.C;                          \
+        *ctl = L.C;                            \
       }                                        \
       return;                                  \
     }                                          \
   } while (0)
 
-  const bool has_cones = (P.n_wave + P.n_lane) > 0;
   const MetricQ unitM{P.qd, 1.0, 0.0, 1};
+#define PROJ(call)                                  \
+  do {                                              \
+    const int _pc = L.pcat;                         \
+    tmark(L, prof, PT_PROJ);                        \
+    call;                                           \
+    tmark(L, prof, _pc);                            \
+  } while (0)
 
   // ------------------------------------------------------------------ init
   if (!L.C.started) {
     // x = Pi_K(x0^) (zb holds the scaled warm start or zeros); a_x = x
-    hw_clear(L, r);
-    for_elem_coords(P, gw, gwaves, [&](long i, bool act) {
-      double x = act ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
-      if (act) { V.x[i] = x; V.ax[i] = x; }
-      hw_add(L, P.R, (int)n, r, i, x, act);
+    hw_clear(L);
+    for_range(c0, c1, [&](long i, bool act) {
+      bool el = act && P.ctype[i] != CT_CONE;
+      double x = el ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
+      if (el) { V.x[i] = x; V.ax[i] = x; }
+      hw_add(L, P.R, n, r, i, x, el);
     });
-    project_cone_items(P, gw, gwaves, true,
-                       [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb);
-    for_cone_coords(P, gw, gwaves, [&](long i, bool act) {
-      double x = act ? V.zb[i] : 0.0;
-      if (act) { V.x[i] = x; V.ax[i] = x; }
-      hw_add(L, P.R, (int)n, r, i, x, act);
-    });
+    if (has_items) {
+      project_items(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
+      for_item_coords(P, IT, [&](long i, bool act) {
+        double x = act ? V.zb[i] : 0.0;
+        if (act) { V.x[i] = x; V.ax[i] = x; }
+        hw_add(L, P.R, n, r, i, x, act);
+      });
+    }
     hw_store(L, r, part, G, rank);
     SYNC_OR_EXIT();
-    // A x, a_y = y
-    for_rows(m, P.a_lanes, gw, gwaves, [&](long row, int sub, bool act) {
-      double ax = spmv_row(P.A_ptr, P.A_col, P.A_val, V.x, row, sub, P.a_lanes, act);
+    for_rows_range(r0, r1, own.lr, [&](long row, int sub, bool act) {
+      double ax = spmv_row(P.A_ptr, P.A_col, P.A_val, V.x, row, sub, own.lr, act);
       if (act && sub == 0) { V.Ax[row] = ax; V.Aa[row] = ax; V.ay[row] = V.y[row]; }
     });
     team_reduce_h(L, part, G, r, L.C.hx);
@@ -377,6 +478,7 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
 
   const bool jac = S.inner == PDHCG_INNER_JACOBI;
   const double rho = S.rho;
+  const int La = own.la, Lr = own.lr;
 
   while (L.C.ktot < A.stop_at && L.C.status == 0) {
     const double omega = L.C.omega;
@@ -387,79 +489,70 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
     const double eps_in = L.C.eps_in;
     const bool tracing = A.T.cap > 0 && L.C.ktot < A.T.cap;
     double* W = P.q_diag ? V.wx : V.u;   // the primal candidate w_x
-    // metric of the prox: diagonal Q -> 1 + tau q; Jacobi -> q + 1/tau
     const MetricQ Mq = P.q_diag ? MetricQ{P.qd, 1.0, tau, 0}
                                 : (jac ? MetricQ{P.qd, 1.0 / tau, 1.0, 0} : unitM);
     const double alpha0 = jac ? 1.0 : 1.0 / (A.qmax + 1.0 / tau);
 
     if (tracing) {
       const long kk = L.C.ktot;
-      for (long i = (long)rank * BLOCK + tid; i < n; i += (long)G * BLOCK) A.T.x[kk * n + i] = V.x[i];
-      for (long i = (long)rank * BLOCK + tid; i < m; i += (long)G * BLOCK) A.T.y[kk * m + i] = V.y[i];
+      for (long i = c0 + tid; i < c1; i += BLOCK) A.T.x[kk * n + i] = V.x[i];
+      for (long l = r0 + tid; l < r1; l += BLOCK) A.T.y[kk * m + l] = V.y[l];
     }
 
     // -------------------------------------------------------------- P1
-    if (!P.q_diag) make_ht(L, P, L.C.hx);
-    {
-      double d2 = 0.0;
-      if (!P.q_diag) hw_clear(L, r);
-      const int La = P.at_lanes;
-      for_rows(n, La, gw, gwaves, [&](long i, int sub, bool act) {
-        const double aty = spmv_row(P.AT_ptr, P.AT_col, P.AT_val, V.y, i, sub, La, act);
-        double xi = act ? V.x[i] : 0.0;
-        const double vi = xi + tau * aty;
-        if (P.q_diag) {
-          if (act && sub == 0) {
-            const double mi = 1.0 + tau * P.qd[i];
-            const double z = (vi - tau * P.c[i]) / mi;
-            if (P.ctype[i] != CT_CONE) V.wx[i] = elem_proj(P.ctype[i], z);
-            else V.zb[i] = z;
-          }
-        } else {
-          double pu = 0.0;
-          if (P.P_ptr) pu = spmv_row(P.P_ptr, P.P_col, P.P_val, V.x, i, sub, La, act);
-          double un = 0.0;
-          bool el = false;
-          if (act && sub == 0) {
-            double ru = 0.0;
-            for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
-            const double g0 = pu + ru + P.c[i] + (xi - vi) / tau;
-            const double di = Mq(i);
-            const double z = xi - alpha0 * g0 / di;
-            V.v[i] = vi;
-            V.gp[i] = g0;
-            V.up[i] = xi;
-            if (P.ctype[i] != CT_CONE) {
-              el = true;
-              un = elem_proj(P.ctype[i], z);
-              V.u[i] = un;
-              d2 += (un - xi) * (un - xi);
-            } else {
-              V.zb[i] = z;
-            }
-          }
-          hw_add(L, P.R, (int)n, r, i, un, el);
-        }
-      });
-      if (!P.q_diag) {
-        const int sl[1] = {SL_DELTA2};
-        block_store(L, &d2, sl, 1, part, G, rank);
-        hw_store(L, r, part, G, rank);
-      }
+    tmark(L, prof, PT_P1);
+    spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.y, V.t1, c0, c1, La);
+    if (!P.q_diag) {
+      if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, V.x, V.t2, c0, c1, La);
+      make_ht(L, P, L.C.hx);
+    } else {
+      __syncthreads();
     }
-    SYNC_OR_EXIT();
-
-    // -------------------------------------------------------------- P2
-    if (has_cones) {
-      if (P.q_diag) {
-        project_cone_items(P, gw, gwaves, false,
-                           [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.wx);
-      } else {
-        double d2 = 0.0;
-        hw_clear(L, r);
-        project_cone_items(P, gw, gwaves, !jac,
-                           [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb);
-        for_cone_coords(P, gw, gwaves, [&](long i, bool act) {
+    if (P.q_diag) {
+      for_range(c0, c1, [&](long i, bool act) {
+        if (!act) return;
+        const double vi = V.x[i] + tau * V.t1[i];
+        const double mi = 1.0 + tau * P.qd[i];
+        const double z = (vi - tau * P.c[i]) / mi;
+        if (P.ctype[i] != CT_CONE) V.wx[i] = elem_proj(P.ctype[i], z);
+        else V.zb[i] = z;
+      });
+      if (has_items) {
+        __syncthreads();
+        PROJ(project_items(P, IT, false, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.wx, V.warm));
+      }
+    } else {
+      double d2 = 0.0;
+      hw_clear(L);
+      for_range(c0, c1, [&](long i, bool act) {
+        double un = 0.0;
+        bool el = false;
+        if (act) {
+          const double xi = V.x[i];
+          const double vi = xi + tau * V.t1[i];
+          double ru = 0.0;
+          for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
+          const double pu = P.P_ptr ? V.t2[i] : 0.0;
+          const double g0 = pu + ru + P.c[i] + (xi - vi) / tau;
+          const double z = xi - alpha0 * g0 / Mq(i);
+          V.v[i] = vi;
+          V.gp[i] = g0;
+          V.up[i] = xi;
+          if (P.ctype[i] != CT_CONE) {
+            el = true;
+            un = elem_proj(P.ctype[i], z);
+            V.u[i] = un;
+            d2 += (un - xi) * (un - xi);
+          } else {
+            V.zb[i] = z;
+          }
+        }
+        hw_add(L, P.R, n, r, i, un, el);
+      });
+      if (has_items) {
+        __syncthreads();
+        PROJ(project_items(P, IT, !jac, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb, V.warm));
+        for_item_coords(P, IT, [&](long i, bool act) {
           double un = 0.0;
           if (act) {
             un = V.zb[i];
@@ -467,25 +560,14 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
             const double dd = un - V.up[i];
             d2 += dd * dd;
           }
-          hw_add(L, P.R, (int)n, r, i, un, act);
+          hw_add(L, P.R, n, r, i, un, act);
         });
-        // add to the P1 partials of this workgroup (same slots)
-        {
-          const int sl[1] = {SL_QMAX};
-          block_store(L, &d2, sl, 1, part, G, rank);
-          __syncthreads();
-          if (tid == 0) part[(size_t)SL_DELTA2 * G + rank] += part[(size_t)SL_QMAX * G + rank];
-          __syncthreads();
-          if ((int)tid < r) {
-            double s = 0.0;
-            for (int w = 0; w < NWAVE; ++w) s += L.hw[w][tid];
-            part[(size_t)(SL_H0 + tid) * G + rank] += s;
-          }
-          __syncthreads();
-        }
       }
-      SYNC_OR_EXIT();
+      const int sl[1] = {SL_DELTA2};
+      block_store(L, &d2, sl, 1, part, G, rank);
+      hw_store(L, r, part, G, rank);
     }
+    SYNC_OR_EXIT();
 
     // -------------------------------------------------------------- inner loop
     int jcount = 0;
@@ -500,25 +582,24 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
       const int jmax = S.fixed_inner > 0 ? S.fixed_inner : S.j_max;
       while (!done && jcount < jmax) {
         // ---- P3: gradient at u, BB reductions
+        tmark(L, prof, PT_P3);
+        if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, V.u, V.t2, c0, c1, La);
         make_ht(L, P, L.hu);
         double acc[3] = {0.0, 0.0, 0.0};
-        const int La = P.at_lanes;
-        for_rows(n, La, gw, gwaves, [&](long i, int sub, bool act) {
-          double pu = 0.0;
-          if (P.P_ptr) pu = spmv_row(P.P_ptr, P.P_col, P.P_val, V.u, i, sub, La, act);
-          if (act && sub == 0) {
-            double ru = 0.0;
-            for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
-            const double ui = V.u[i];
-            const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
-            const double si = ui - V.up[i];
-            const double dg = gc - V.gp[i];
-            const double di = Mq(i);
-            acc[0] += si * (di * si);
-            acc[1] += si * dg;
-            acc[2] += si * si;
-            V.g[i] = gc;
-          }
+        for_range(c0, c1, [&](long i, bool act) {
+          if (!act) return;
+          double ru = 0.0;
+          for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
+          const double ui = V.u[i];
+          const double pu = P.P_ptr ? V.t2[i] : 0.0;
+          const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
+          const double si = ui - V.up[i];
+          const double dg = gc - V.gp[i];
+          const double di = Mq(i);
+          acc[0] += si * (di * si);
+          acc[1] += si * dg;
+          acc[2] += si * si;
+          V.g[i] = gc;
         });
         {
           const int sl[3] = {SL_SJS, SL_SDG, SL_SS};
@@ -533,11 +614,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
         const double num = jac ? L.scal[SL_SJS] : L.scal[SL_SS];
         const double alpha = den > 0.0 ? num / den : 1.0;
         // ---- P4: projected step
+        tmark(L, prof, PT_P4);
         double d2 = 0.0;
-        hw_clear(L, r);
-        for_elem_coords(P, gw, gwaves, [&](long i, bool act) {
+        hw_clear(L);
+        for_range(c0, c1, [&](long i, bool act) {
+          const bool el = act && P.ctype[i] != CT_CONE;
           double un = 0.0;
-          if (act) {
+          if (el) {
             const double ui = V.u[i];
             const double gi = V.g[i];
             un = elem_proj(P.ctype[i], ui - alpha * gi / Mq(i));
@@ -546,12 +629,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
             V.gp[i] = gi;
             V.u[i] = un;
           }
-          hw_add(L, P.R, (int)n, r, i, un, act);
+          hw_add(L, P.R, n, r, i, un, el);
         });
-        if (has_cones) {
-          project_cone_items(P, gw, gwaves, !jac,
-                             [&](long st) { return StepSrc{V.u, V.g, Mq, alpha, st}; }, V.zb);
-          for_cone_coords(P, gw, gwaves, [&](long i, bool act) {
+        if (has_items) {
+          PROJ(project_items(P, IT, !jac,
+                             [&](long st) { return StepSrc{V.u, V.g, Mq, alpha, st}; }, V.zb, V.warm,
+                             prof ? &L.pt[PT_WCALL] : nullptr));
+          for_item_coords(P, IT, [&](long i, bool act) {
             double un = 0.0;
             if (act) {
               un = V.zb[i];
@@ -561,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
               V.gp[i] = V.g[i];
               V.u[i] = un;
             }
-            hw_add(L, P.R, (int)n, r, i, un, act);
+            hw_add(L, P.R, n, r, i, un, act);
           });
         }
         {
@@ -581,14 +665,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
     }
 
     // -------------------------------------------------------------- P6
-    const double c1 = (double)(k + 1) / (double)(k + 2);
-    const double c3 = 1.0 / (double)(k + 2);
+    tmark(L, prof, PT_P6);
+    const double c1h = (double)(k + 1) / (double)(k + 2);
+    const double c3h = 1.0 / (double)(k + 2);
     {
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      // rows: A w_x, dual candidate
-      const int La = P.a_lanes;
-      for_rows(m, La, gw, gwaves, [&](long l, int sub, bool act) {
-        const double aw = spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, La, act);
+      for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
+        const double aw = spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
           const double wy = yl + sigma * (P.b[l] - (2.0 * aw - axl));
@@ -605,16 +688,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
             const double my = wy - V.ay[l];
             acc[4] += my * my;                           // SL_MOVY2
           } else {
-            V.y[l] = c1 * (2.0 * rho * wy + (1.0 - 2.0 * rho) * yl) + c3 * V.ay[l];
-            V.Ax[l] = c1 * (2.0 * rho * aw + (1.0 - 2.0 * rho) * axl) + c3 * V.Aa[l];
+            V.y[l] = c1h * (2.0 * rho * wy + (1.0 - 2.0 * rho) * yl) + c3h * V.ay[l];
+            V.Ax[l] = c1h * (2.0 * rho * aw + (1.0 - 2.0 * rho) * axl) + c3h * V.Aa[l];
           }
         }
       });
-      // coordinates
-      if (!check) hw_clear(L, r);
-      for (long base = (long)gw * 64; base < n; base += (long)gwaves * 64) {
-        const long i = base + lane;
-        const bool act = i < n;
+      if (!check) hw_clear(L);
+      for_range(c0, c1, [&](long i, bool act) {
         double xn = 0.0;
         if (act) {
           const double xi = V.x[i], wi = W[i];
@@ -626,13 +706,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
             acc[6] += mx * mx;                           // SL_MOVX2
             acc[7] += P.c[i] * wi;                       // SL_CX
           } else {
-            xn = c1 * (2.0 * rho * wi + (1.0 - 2.0 * rho) * xi) + c3 * V.ax[i];
-            acc[5] += (xn - xi) * (xn - xi);             // SL_XMOV2 (stored below)
+            xn = c1h * (2.0 * rho * wi + (1.0 - 2.0 * rho) * xi) + c3h * V.ax[i];
+            acc[5] += (xn - xi) * (xn - xi);             // SL_XMOV2
             V.x[i] = xn;
           }
         }
-        if (!check) hw_add(L, P.R, (int)n, r, i, xn, act);
-      }
+        if (!check) hw_add(L, P.R, n, r, i, xn, act);
+      });
       if (check) {
         const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
         block_store(L, acc, sl, 8, part, G, rank);
@@ -659,69 +739,67 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
       if (tid == 0) {
         L.C.eps_in = fmin(L.C.eps_in, fmax(S.gamma_in * sqrt(L.scal[SL_XMOV2]) / tau, S.eps_min));
         L.C.k = k + 1;
+        if (tracing && rank == 0) {
+          double* sc = A.T.sc + (kt1 - 1) * 8;
+          sc[0] = tau; sc[1] = sigma; sc[2] = omega; sc[3] = eps_in;
+          sc[4] = jcount; sc[5] = 0.0; sc[6] = 0.0; sc[7] = 0.0;
+        }
       }
       __syncthreads();
-      if (tracing && rank == 0 && tid == 0) {
-        double* sc = A.T.sc + (L.C.ktot - 1) * 8;
-        sc[0] = tau; sc[1] = sigma; sc[2] = omega; sc[3] = eps_in;
-        sc[4] = jcount; sc[5] = 0.0; sc[6] = 0.0; sc[7] = 0.0;
-      }
       continue;
     }
 
     // ---------------------------------------------------------- check
+    tmark(L, prof, PT_CHECK);
     {
       const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
       team_reduce(L, part, G, sl, 8);
     }
-    // R^ w_x: for the Jacobi path it is the last inner R^ u; diagonal Q has r = 0
-    // C1: dual slack s = Q w + c - A^T w_y
     {
+      // dual slack s = Q w + c - A^T w_y on own coordinates; R^ w_x is the
+      // last inner R^ u (diagonal Q has r = 0)
+      spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, c0, c1, La);
+      if (!P.q_diag && P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, W, V.t2, c0, c1, La);
       if (!P.q_diag) make_ht(L, P, L.hu);
+      else __syncthreads();
       double acc[2] = {0.0, 0.0};
-      const int La = P.at_lanes;
-      for_rows(n, La, gw, gwaves, [&](long i, int sub, bool act) {
-        const double aty = spmv_row(P.AT_ptr, P.AT_col, P.AT_val, V.wy, i, sub, La, act);
-        double qw = 0.0;
+      for_range(c0, c1, [&](long i, bool act) {
+        if (!act) return;
+        const double wi = W[i];
+        double qw;
         if (P.q_diag) {
-          if (act) qw = P.qd[i] * W[i];
+          qw = P.qd[i] * wi;
         } else {
-          if (P.P_ptr) qw = spmv_row(P.P_ptr, P.P_col, P.P_val, W, i, sub, La, act);
-          if (act) for (int kk = 0; kk < r; ++kk) qw += P.R[(size_t)kk * n + i] * L.ht[kk];
+          qw = P.P_ptr ? V.t2[i] : 0.0;
+          for (int kk = 0; kk < r; ++kk) qw += P.R[(size_t)kk * n + i] * L.ht[kk];
         }
-        if (act && sub == 0) {
-          const double wi = W[i];
-          const double si = qw + P.c[i] - aty;
-          acc[0] += wi * qw;                               // SL_XQX
-          const double so = P.nu_c * P.Sx[i] * si;
-          const uint8_t ct = P.ctype[i];
-          if (ct == CT_FREE) acc[1] += so * so;
-          else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
-          else V.s[i] = si;
-        }
+        const double si = qw + P.c[i] - V.t1[i];
+        acc[0] += wi * qw;                               // SL_XQX
+        const double so = P.nu_c * P.Sx[i] * si;
+        const uint8_t ct = P.ctype[i];
+        if (ct == CT_FREE) acc[1] += so * so;
+        else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
+        else V.s[i] = si;
       });
+      if (has_items) {
+        __syncthreads();
+        project_items(P, IT, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb,
+                      V.warm + (P.n_wave + P.n_lane));
+        for_item_coords(P, IT, [&](long i, bool act) {
+          if (act) {
+            const double f = P.nu_c * P.Sx[i] * V.zb[i];
+            acc[1] += f * f;
+          }
+        });
+      }
       const int sl[2] = {SL_XQX, SL_RD2};
       block_store(L, acc, sl, 2, part, G, rank);
     }
     SYNC_OR_EXIT();
-    if (has_cones) {
-      double rd = 0.0;
-      project_cone_items(P, gw, gwaves, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb);
-      for_cone_coords(P, gw, gwaves, [&](long i, bool act) {
-        if (act) {
-          const double f = P.nu_c * P.Sx[i] * V.zb[i];
-          rd += f * f;
-        }
-      });
-      const int sl[1] = {SL_QMAX};
-      block_store(L, &rd, sl, 1, part, G, rank);
-      SYNC_OR_EXIT();
-    }
     {
-      int sl[3] = {SL_XQX, SL_RD2, SL_QMAX};
-      team_reduce(L, part, G, sl, has_cones ? 3 : 2);
+      const int sl[2] = {SL_XQX, SL_RD2};
+      team_reduce(L, part, G, sl, 2);
     }
-    bool restart = false;
     if (tid == 0) {
       Ctl& C = L.C;
       const double* sc = L.scal;
@@ -733,10 +811,9 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
                 ((double)(k + 1) >= S.beta_a * (double)kt1);
       C.Eprev = E;
       C.lastE = E;
-      const double rd2 = sc[SL_RD2] + (has_cones ? sc[SL_QMAX] : 0.0);
       const double scale = P.nu_b * P.nu_c;
       C.rel_p = sqrt(sc[SL_RP2]) / (1.0 + P.norm_b);
-      C.rel_d = sqrt(rd2) / (1.0 + P.norm_c);
+      C.rel_d = sqrt(sc[SL_RD2]) / (1.0 + P.norm_c);
       C.pobj = scale * (0.5 * sc[SL_XQX] + sc[SL_CX]);
       C.dobj = scale * (sc[SL_BY] - 0.5 * sc[SL_XQX]);
       C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
@@ -764,26 +841,24 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
       }
     }
     __syncthreads();
-    restart = L.done != 0;
+    const bool restart = L.done != 0;
     if (L.C.status != 0) break;
 
     // ---------------------------------------------------------- restart or Halpern
+    tmark(L, prof, PT_HALP);
     {
       double xm = 0.0;
-      if (!restart) hw_clear(L, r);
-      for_rows(m, 1, gw, gwaves, [&](long l, int sub, bool act) {
-        if (!act) return;
+      if (!restart) hw_clear(L);
+      for (long l = r0 + tid; l < r1; l += BLOCK) {
         const double wy = V.wy[l], aw = V.Aw[l];
         if (restart) {
           V.y[l] = wy; V.ay[l] = wy; V.Ax[l] = aw; V.Aa[l] = aw;
         } else {
-          V.y[l] = c1 * (2.0 * rho * wy + (1.0 - 2.0 * rho) * V.y[l]) + c3 * V.ay[l];
-          V.Ax[l] = c1 * (2.0 * rho * aw + (1.0 - 2.0 * rho) * V.Ax[l]) + c3 * V.Aa[l];
+          V.y[l] = c1h * (2.0 * rho * wy + (1.0 - 2.0 * rho) * V.y[l]) + c3h * V.ay[l];
+          V.Ax[l] = c1h * (2.0 * rho * aw + (1.0 - 2.0 * rho) * V.Ax[l]) + c3h * V.Aa[l];
         }
-      });
-      for (long base = (long)gw * 64; base < n; base += (long)gwaves * 64) {
-        const long i = base + lane;
-        const bool act = i < n;
+      }
+      for_range(c0, c1, [&](long i, bool act) {
         double xn = 0.0;
         if (act) {
           const double wi = W[i];
@@ -791,13 +866,13 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
             V.x[i] = wi; V.ax[i] = wi;
           } else {
             const double xi = V.x[i];
-            xn = c1 * (2.0 * rho * wi + (1.0 - 2.0 * rho) * xi) + c3 * V.ax[i];
+            xn = c1h * (2.0 * rho * wi + (1.0 - 2.0 * rho) * xi) + c3h * V.ax[i];
             xm += (xn - xi) * (xn - xi);
             V.x[i] = xn;
           }
         }
-        if (!restart) hw_add(L, P.R, (int)n, r, i, xn, act);
-      }
+        if (!restart) hw_add(L, P.R, n, r, i, xn, act);
+      });
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &xm, sl, 1, part, G, rank);
@@ -821,8 +896,42 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
       __syncthreads();
     }
   }
-  if (rank == 0 && tid == 0) *A.ctl = L.C;
 #undef SYNC_OR_EXIT
+#undef PROJ
+}
+
+// ---------------------------------------------------------------------------
+// single-problem kernel: the whole grid is one team
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
+  __shared__ Lds L;
+  const int rank = blockIdx.x, G = gridDim.x;
+  if (threadIdx.x < PT_COUNT) L.pt[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) {
+    L.C = *A.ctl;
+    L.pcat = PT_INIT;
+    L.plast = wall_clock64();
+    L.epoch = __hip_atomic_load(&A.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (L.C.status != 0) return;
+  const bool prof = A.profile != 0;
+  const DevProblem& P = A.P;
+  Own own;
+  own.c0 = P.part_c[rank];
+  own.c1 = P.part_c[rank + 1];
+  own.r0 = P.part_r[rank];
+  own.r1 = P.part_r[rank + 1];
+  own.it = Items{P.part_w[rank], P.part_w[rank + 1], P.part_l[rank], P.part_l[rank + 1],
+                 (int)P.part_lanes[4 * rank + 2]};
+  own.la = P.part_lanes[4 * rank + 0];
+  own.lr = P.part_lanes[4 * rank + 1];
+  GridTeam T{A.bar, A.spin_limit, rank, G};
+  run_solver(A, P, A.V, A.ctl, T, L, own, prof);
+  tmark(L, prof, PT_INIT);
+  __syncthreads();
+  if (prof && threadIdx.x < PT_COUNT) A.ptimes[(size_t)rank * PT_COUNT + threadIdx.x] += L.pt[threadIdx.x];
+  if (rank == 0 && threadIdx.x == 0 && L.C.status != PDHCG_ABORTED) *A.ctl = L.C;
 }
 
 // ---------------------------------------------------------------------------
@@ -831,13 +940,14 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
 __global__ __launch_bounds__(BLOCK) void spmv_kernel(const int64_t* ptr, const int* col,
                                                      const double* val, const double* x,
                                                      double* y, long rows, int Lw) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gw = blockIdx.x * NWAVE + wv, gwaves = gridDim.x * NWAVE;
-  for_rows(rows, Lw, gw, gwaves, [&](long row, int sub, bool act) {
-    double s = spmv_row(ptr, col, val, x, row, sub, Lw, act);
+  const int groups = BLOCK / Lw;
+  const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
+  for (long base = (long)blockIdx.x * groups; base < rows; base += (long)gridDim.x * groups) {
+    const long row = base + gid;
+    const bool act = row < rows;
+    const double s = spmv_row(ptr, col, val, x, row, sub, Lw, act);
     if (act && sub == 0) y[row] = s;
-  });
-  (void)lane;
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void sumsq_partial_kernel(const double* x, long n, double* part) {
@@ -854,11 +964,10 @@ __global__ __launch_bounds__(BLOCK) void sumsq_partial_kernel(const double* x, l
   }
 }
 
-// out[0] = sqrt(sum part); x2 = x / out[0] (if scale_out)
 __global__ __launch_bounds__(BLOCK) void finish_norm_kernel(const double* part, int np, double* out) {
-  double s = 0.0;
-  for (int j = threadIdx.x; j < np; j += 64) s += part[j];
   if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < np; j += 64) s += part[j];
     s = wave_sum(s);
     if (threadIdx.x == 0) out[0] = sqrt(s);
   }
@@ -901,7 +1010,7 @@ hipError_t max_coop_grid(int* out) {
 hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, const double* x,
                        double* y, long rows, int Lw, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  long per = 64 / Lw * NWAVE;
+  long per = BLOCK / Lw;
   long grid = (rows + per - 1) / per;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(spmv_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, ptr, col, val, x, y,
