@@ -26,6 +26,27 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one solve_kernel launch on the default workload, from two
+# rocprofv3 counter runs (FETCH_SIZE x 1.99978, WRITE_SIZE x 1.0: the factors
+# that make a 256 MiB device copy read and write 256 MiB).  Valid only for the
+# kernel sources whose hash is recorded, at the recorded grid; otherwise the
+# bench reports null.
+MEASURED_TRAFFIC = {
+    "workload": "mixed_cone", "grid": 196, "iterations": 448,
+    "sources_sha256": "152f98099fcc80254a7ce6474e5eb03bab5305ef3069842a2aefef0f87e8d800",
+    "bytes_per_launch": 14258337.4375 * 1024 * 1.99978 + 16720173.3125 * 1024 * 1.0,
+}
+KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_09159_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 METRIC = "time-to-1e-6 rel KKT (s) + PDHG iters/s; FP32/batched/warm vs plain FP64"
 
 
@@ -82,9 +103,10 @@ def cpu_baseline(prob, budget_s=15.0):
             t0 = time.perf_counter()
             r = pdhg.solve(prob, pdhg.Settings(max_iter=iters), S=S)
             dt = time.perf_counter() - t0
-            if dt >= budget_s / 3 or iters >= 100000:
+            if dt >= 0.6 * budget_s or iters >= 100000:
                 break
-            iters = int(min(iters * max(2.0, 0.5 * budget_s / max(dt, 1e-3)), 100000))
+            grow = min(max(1.25, budget_s / max(dt, 1e-3)), 8.0)
+            iters = int(min(iters * grow, 100000))
     return dict(value=r.iterations / dt, unit="PDHG iters/s", cores=1, kind="oracle",
                 sample=f"first {r.iterations} outer iterations of the same instance "
                        f"({dt:.1f}s, {r.inner_iterations} inner steps; setup {t_setup:.1f}s "
@@ -100,6 +122,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
@@ -113,6 +137,12 @@ def main():
         from paper_2608_09159_amd import build
         build.build()
     prob, wname = workload(args.workload)
+    if args.calibrate_copy:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream)
     res = None
@@ -129,6 +159,12 @@ def main():
     iters = sum(r["iterations"] for r in runs)
     inner = sum(r["inner_iterations"] for r in runs)
     ksum = sum(r["kernel_s"] for r in runs)
+    traffic = None
+    grid = runs[-1]["grid_dim"]
+    mt = MEASURED_TRAFFIC
+    if (args.workload == mt["workload"] and kernel_sources_hash() == mt["sources_sha256"]
+            and grid == mt["grid"] and all(r["iterations"] == mt["iterations"] for r in runs)):
+        traffic = mt["bytes_per_launch"]
     launches = sum(r["kernel_launches"] for r in runs)
     checks = sum(math.ceil(r["iterations"] / 64) + r["restarts"] + 1 for r in runs)
     alg_bytes = bytes_model(prob, iters, inner, checks)
@@ -155,8 +191,10 @@ def main():
         "status": last["status"],
         "rel_kkt": max(last["rel_primal"], last["rel_dual"], last["rel_gap"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
                      "kernel": "solve_kernel", "kernel_avg_launch_ms": 1e3 * ksum / launches,
+                     "launch": [grid, runs[-1]["block_dim"]],
                      "algorithmic_bytes_per_iteration": alg_bytes / iters},
     }
     if not args.no_cpu:

@@ -164,6 +164,8 @@ typedef struct {
     /* device time of the solver launches (settings.time_kernels = 1) */
     double  kernel_s;
     int64_t kernel_launches;
+    int32_t grid_dim;             /* workgroups of the solver launch          */
+    int32_t block_dim;            /* threads per workgroup                    */
 } pdhcg_result;
 
 /* Per-iteration record for parity checks, in the library's scaled space

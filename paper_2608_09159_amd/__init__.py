@@ -73,7 +73,8 @@ class ResultC(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("omega", C.c_double),
                 ("a_norm", C.c_double), ("x", _dp), ("y", _dp), ("s", _dp),
-                ("kernel_s", C.c_double), ("kernel_launches", C.c_int64)]
+                ("kernel_s", C.c_double), ("kernel_launches", C.c_int64),
+                ("grid_dim", C.c_int32), ("block_dim", C.c_int32)]
 
 
 class TraceC(C.Structure):
@@ -212,7 +213,8 @@ class Handle:
                    rel_primal=res.rel_primal, rel_dual=res.rel_dual, rel_gap=res.rel_gap,
                    primal_obj=res.primal_obj, dual_obj=res.dual_obj, setup_s=res.setup_s,
                    solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y,
-                   kernel_s=res.kernel_s, kernel_launches=res.kernel_launches)
+                   kernel_s=res.kernel_s, kernel_launches=res.kernel_launches,
+                   grid_dim=res.grid_dim, block_dim=res.block_dim)
         if want_s:
             out["s"] = s
         return out

@@ -536,6 +536,8 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   }
   res->kernel_s = ksum;
   res->kernel_launches = nlaunch;
+  res->grid_dim = I->grid;
+  res->block_dim = block_size();
   if (h->s.verbose & 8) {
     static const char* names[PT_COUNT] = {"init", "P1", "P2", "P3", "P4", "P6", "check",
                                           "halpern", "barrier", "proj", "wcall", "ncall"};
