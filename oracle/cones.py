@@ -16,7 +16,9 @@ M = cI reduces to the Euclidean projection; the closed forms printed in
 Appendix C (box/R+, SOC, RSOC through the rotation U, the SOC r_t = 0 case,
 the RSOC singular case, the EXP r0 <= 0, s0 <= 0 case, the POW r_z = 0 case);
 POW with alpha = 1/2 against the RSOC M-norm projection; brute force over
-boundary points for tiny inputs.
+boundary points for tiny inputs; the EXP closest-point fallback (used only
+where the root bracket degenerates, next to the polar cone) against the root
+method on generic inputs, and near-polar inputs projecting to ~0.
 
 Membership tests are exact floating-point comparisons; the projection is
 continuous, so a borderline decision changes the result only at rounding
@@ -553,7 +555,74 @@ def exp_metric_one(r, m=(1.0, 1.0, 1.0)):
         u = point(x)
         if u[1] >= 0:
             return u
-    raise FloatingPointError(f"exp projection: no bracket for r={r}, m={m}")
+    # No admissible sign change survives in floating point: r lies within
+    # rounding of the polar cone (Pi(r) ~ 0) or of the ray family's ends.
+    # Fall back to the definition of the projection (closest point of K).
+    return exp_closest_direct(r0, s0, t0, mr, ms, mt)
+
+
+def exp_closest_direct(r0, s0, t0, mr=1.0, ms=1.0, mt=1.0):
+    """Closest point of K_exp to r in the diagonal M-norm: r itself when
+    r is in K, else by direct comparison of the pieces of the cone's
+    boundary: the apex 0, the face
+    {(a, 0, b): a <= 0, b >= 0} (its M-projection clamps componentwise), and
+    the rays (rho, 1, e^rho), whose M-projection is eta(rho) (rho, 1, e^rho)
+    with eta = <r, d>_M / |d|_M^2 when positive.  The ray parameter is
+    located on a grid (uniform on [-60, 60], logarithmic tails to 1e12) and
+    refined by golden-section search on the distance.  Used where the root
+    bracket of h_M degenerates; accurate to about sqrt(eps) in rho."""
+    vals = (r0, s0, t0, mr, ms, mt)
+    if not all(math.isfinite(v) for v in vals):
+        raise FloatingPointError(f"exp projection: non-finite input {vals}")
+
+    if in_exp((r0, s0, t0)):
+        return np.array([r0, s0, t0])
+
+    def dist2(u):
+        return mr * (u[0] - r0) ** 2 + ms * (u[1] - s0) ** 2 + mt * (u[2] - t0) ** 2
+
+    def ray_point(x):
+        eta, _, eta_e = _exp_eta_h(x, r0, s0, t0, mr, ms, mt)
+        if not eta > 0:
+            return None
+        return np.array([eta * x, eta, eta_e])
+
+    best = np.zeros(3)
+    face = np.array([min(r0, 0.0), 0.0, max(t0, 0.0)])
+    if dist2(face) < dist2(best):
+        best = face
+    tails = np.logspace(math.log10(60.0), 12.0, 200)
+    grid = np.concatenate([-tails[::-1], np.linspace(-60.0, 60.0, 4801), tails])
+    d_grid = np.full(grid.size, np.inf)
+    for k, x in enumerate(grid):
+        u = ray_point(float(x))
+        if u is not None:
+            d_grid[k] = dist2(u)
+    k = int(np.argmin(d_grid))
+    if math.isfinite(d_grid[k]):
+        lo, hi = float(grid[max(k - 1, 0)]), float(grid[min(k + 1, grid.size - 1)])
+        g = (math.sqrt(5.0) - 1.0) / 2.0
+
+        def f(x):
+            u = ray_point(x)
+            return dist2(u) if u is not None else math.inf
+        a, b = lo, hi
+        c, d = b - g * (b - a), a + g * (b - a)
+        fc, fd = f(c), f(d)
+        for _ in range(200):
+            if fc <= fd:
+                b, d, fd = d, c, fc
+                c = b - g * (b - a)
+                fc = f(c)
+            else:
+                a, c, fc = c, d, fd
+                d = a + g * (b - a)
+                fd = f(d)
+        for x in (c, d, float(grid[k])):
+            u = ray_point(x)
+            if u is not None and dist2(u) < dist2(best):
+                best = u
+    return best
 
 
 # ----------------------------------------------------------------------------

@@ -313,6 +313,38 @@ def test_exp_brute_force():
         assert du <= bval + 1e-9 * max(1.0, bval), (r, m, u, bu)
 
 
+def test_exp_direct_closest_point_agrees():
+    """The closest-point fallback (direct search over the boundary pieces)
+    and the root-of-h_M method agree on generic inputs, inside and outside K,
+    in both metrics."""
+    rng = np.random.default_rng(8)
+    for r in exp_inputs(rng, 150):
+        m = random_metric(3, rng)
+        a = C.exp_metric_one(r, m)
+        b = C.exp_closest_direct(*r, *m)
+        assert np.linalg.norm(a - b) <= 1e-7 * max(1.0, np.linalg.norm(r)), (r, m, a, b)
+
+
+def test_exp_near_polar_boundary():
+    """Inputs within rounding of the polar cone -K^* (as the dual slack of a
+    solved EXP block is) project to (nearly) zero and satisfy the KKT
+    characterisation; the bracket of h_M degenerates there."""
+    rng = np.random.default_rng(9)
+    cases = [(np.array([1.22744381, 0.97589908, -1.0]), np.ones(3))]
+    for i in range(60):
+        a = -abs(rng.standard_normal()) * 10.0 ** rng.uniform(-2, 2)
+        b = rng.standard_normal() * abs(a)
+        c = -a * math.exp(b / a) / math.e               # (a, b, c) on the boundary of K^*
+        m = np.ones(3) if i % 2 else random_metric(3, rng)
+        # -M r on the boundary of K^*, up to relative 1e-13
+        r = -np.array([a, b, c]) / m * (1.0 + 1e-13 * rng.standard_normal(3))
+        cases.append((r, m))
+    for r, m in cases:
+        u = C.exp_metric_one(r, m)
+        assert np.linalg.norm(u) <= 1e-9 * np.linalg.norm(r), (r, m, u)
+        check_kkt("exp", r, u, m, tol=1e-7)
+
+
 # ---------------------------------------------------------------------------
 # POW
 # ---------------------------------------------------------------------------
