@@ -77,7 +77,12 @@ extern "C" {
 #define PDHCG_INNER_JACOBI 0  /* eq. jacobi-bb-step                           */
 #define PDHCG_INNER_EUCLID 1  /* eq. bb-step                                  */
 #define PDHCG_PREC_FP64   0
-#define PDHCG_PREC_FP32   1   /* FP32 matrix sweeps, FP64 state and decisions */
+#define PDHCG_PREC_FP32   1   /* FP32 copies of A, A^T, P, R for the bulk
+                                 sweeps (A^T y, P u, R u, A w; FP32 products
+                                 and row sums); FP64 iterates, reductions,
+                                 restart and KKT checks (checks use the FP64
+                                 data) and cone root-finding; then an FP64
+                                 polish (single problems only)              */
 
 typedef struct {
     int32_t n;                    /* primal dimension                         */
@@ -144,6 +149,16 @@ typedef struct {
     int32_t verbose;
     int32_t time_kernels;         /* 1: time every solver launch with HIP
                                      events on `stream` (result.kernel_s)     */
+    int32_t autotune;             /* batches: 1 = choose the lanes-per-row
+                                     mapping of the A and A^T products by
+                                     timing candidate mappings at setup;
+                                     0 = fixed rule (about 2 nonzeros per
+                                     lane).  Ignored for single problems.     */
+    int32_t tune_iters;           /* outer iterations per autotuner probe (64)*/
+    double  fp32_tol;             /* PDHCG_PREC_FP32: tolerance of the FP32
+                                     phase; the FP64 polish then restarts at
+                                     its candidate and runs to tol
+                                     (<= 0: 10 * tol)                         */
 } pdhcg_settings;
 
 typedef struct {
@@ -166,6 +181,8 @@ typedef struct {
     int64_t kernel_launches;
     int32_t grid_dim;             /* workgroups of the solver launch          */
     int32_t block_dim;            /* threads per workgroup                    */
+    int64_t polish_iterations;    /* FP32 mode: outer iterations of the FP64
+                                     polish (included in `iterations`)      */
 } pdhcg_result;
 
 /* Per-iteration record for parity checks, in the library's scaled space
@@ -199,10 +216,18 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count,
  * res->x, res->y, res->s.  Returns PDHCG_E_STATE for a batch handle.        */
 int pdhcg_solve(void* h, const double* x0, const double* y0, pdhcg_result* res);
 
-/* Solve every problem of a batch handle in one persistent launch, one
- * workgroup per instance with per-instance step sizes, restarts and inner
- * tolerances.  x0s/y0s: NULL or arrays of `count` host pointers (each may be
- * NULL).  res: array of `count` results (their x/y/s pointers may be set).  */
+/* Solve every problem of a batch handle (count > 1 at setup) in one
+ * persistent launch, replayed from a HIP graph: each workgroup takes the next
+ * instance from a device queue (largest first) and runs the whole restarted
+ * PDHG method on it with that instance's own step sizes, primal weight,
+ * restarts and inner tolerance, then takes the next.  Every instance runs to
+ * its own termination (tol, max_iter); settings.time_limit bounds the whole
+ * launch (instances still running then report PDHCG_TIME_LIMIT).
+ * x0s/y0s: NULL or arrays of `count` host pointers (each may be NULL; original
+ * space).  res: array of `count` results; their x/y/s pointers may be set.
+ * kernel_s of res[0] holds the device time of the launch; setup_s and
+ * solve_s are those of the whole batch.  For a single-problem handle this is
+ * pdhcg_solve on res[0].                                                     */
 int pdhcg_solve_batch(void* h, const double* const* x0s, const double* const* y0s,
                       pdhcg_result* res);
 

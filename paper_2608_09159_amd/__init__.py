@@ -10,6 +10,8 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
     default_settings(**overrides) -> Settings
     setup(problem, settings) -> Handle       (pdhcg_setup, count == 1)
     Handle.solve(x0=None, y0=None) -> dict    (pdhcg_solve)
+    setup_batch(problems, settings) -> BatchHandle   (pdhcg_setup, count > 1)
+    BatchHandle.solve(x0s=None, y0s=None) -> [dict]  (pdhcg_solve_batch)
     Handle.trace(count) -> dict               (pdhcg_get_trace)
     Handle.scaling() -> dict                  (pdhcg_get_scaling)
     Handle.free()                             (pdhcg_free)
@@ -63,7 +65,8 @@ class Settings(C.Structure):
                 ("precision", C.c_int32), ("trace_iters", C.c_int32), ("block_dim", C.c_int32),
                 ("grid_dim", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
                 ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
-                ("time_kernels", C.c_int32)]
+                ("time_kernels", C.c_int32), ("autotune", C.c_int32),
+                ("tune_iters", C.c_int32), ("fp32_tol", C.c_double)]
 
 
 class ResultC(C.Structure):
@@ -74,7 +77,8 @@ class ResultC(C.Structure):
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("omega", C.c_double),
                 ("a_norm", C.c_double), ("x", _dp), ("y", _dp), ("s", _dp),
                 ("kernel_s", C.c_double), ("kernel_launches", C.c_int64),
-                ("grid_dim", C.c_int32), ("block_dim", C.c_int32)]
+                ("grid_dim", C.c_int32), ("block_dim", C.c_int32),
+                ("polish_iterations", C.c_int64)]
 
 
 class TraceC(C.Structure):
@@ -208,23 +212,15 @@ class Handle:
         y0a = np.ascontiguousarray(y0, dtype=np.float64) if y0 is not None else None
         _check(lib.pdhcg_solve(self.ptr, _ptr(x0a, C.c_double), _ptr(y0a, C.c_double),
                                C.byref(res)), "pdhcg_solve")
-        out = dict(status=STATUS.get(res.status, str(res.status)), iterations=res.iterations,
-                   inner_iterations=res.inner_iterations, restarts=res.restarts,
-                   rel_primal=res.rel_primal, rel_dual=res.rel_dual, rel_gap=res.rel_gap,
-                   primal_obj=res.primal_obj, dual_obj=res.dual_obj, setup_s=res.setup_s,
-                   solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y,
-                   kernel_s=res.kernel_s, kernel_launches=res.kernel_launches,
-                   grid_dim=res.grid_dim, block_dim=res.block_dim)
-        if want_s:
-            out["s"] = s
-        return out
+        return _result_dict(res, x, y, s)
 
-    def trace(self, count):
+    def trace(self, count, inst=0):
         lib = load()
+        n, m = self._dims(inst)
         t = TraceC()
         t.count = count
-        bufs = dict(x=np.zeros((count, self.n)), y=np.zeros((count, self.m)),
-                    wx=np.zeros((count, self.n)), wy=np.zeros((count, self.m)),
+        bufs = dict(x=np.zeros((count, n)), y=np.zeros((count, m)),
+                    wx=np.zeros((count, n)), wy=np.zeros((count, m)),
                     tau=np.zeros(count), sigma=np.zeros(count), omega=np.zeros(count),
                     eps_in=np.zeros(count), E=np.zeros(count))
         ibufs = dict(inner=np.zeros(count, np.int32), restart=np.zeros(count, np.int32),
@@ -233,16 +229,22 @@ class Handle:
             setattr(t, k, _ptr(v, C.c_double))
         for k, v in ibufs.items():
             setattr(t, k, _ptr(v, C.c_int32))
-        _check(lib.pdhcg_get_trace(self.ptr, 0, C.byref(t)), "pdhcg_get_trace")
+        _check(lib.pdhcg_get_trace(self.ptr, inst, C.byref(t)), "pdhcg_get_trace")
         out = {k: v[:t.count] for k, v in {**bufs, **ibufs}.items()}
         out["count"] = t.count
         return out
 
-    def scaling(self):
+    def _dims(self, inst):
+        if inst != 0:
+            raise IndexError(inst)
+        return self.n, self.m
+
+    def scaling(self, inst=0):
         lib = load()
-        Sx, Sy = np.zeros(self.n), np.zeros(self.m)
+        n, m = self._dims(inst)
+        Sx, Sy = np.zeros(n), np.zeros(m)
         vals = [C.c_double() for _ in range(4)]
-        _check(lib.pdhcg_get_scaling(self.ptr, 0, _ptr(Sx, C.c_double), _ptr(Sy, C.c_double),
+        _check(lib.pdhcg_get_scaling(self.ptr, inst, _ptr(Sx, C.c_double), _ptr(Sy, C.c_double),
                                      *[C.pointer(v) for v in vals]), "pdhcg_get_scaling")
         return dict(Sx=Sx, Sy=Sy, nu_b=vals[0].value, nu_c=vals[1].value, eta=vals[2].value,
                     omega0=vals[3].value)
@@ -257,6 +259,77 @@ class Handle:
             self.free()
         except Exception:
             pass
+
+
+def _result_dict(res, x, y, s):
+    out = dict(status=STATUS.get(res.status, str(res.status)), iterations=res.iterations,
+               inner_iterations=res.inner_iterations, restarts=res.restarts,
+               rel_primal=res.rel_primal, rel_dual=res.rel_dual, rel_gap=res.rel_gap,
+               primal_obj=res.primal_obj, dual_obj=res.dual_obj, setup_s=res.setup_s,
+               solve_s=res.solve_s, omega=res.omega, a_norm=res.a_norm, x=x, y=y,
+               kernel_s=res.kernel_s, kernel_launches=res.kernel_launches,
+               grid_dim=res.grid_dim, block_dim=res.block_dim,
+               polish_iterations=res.polish_iterations)
+    if s is not None:
+        out["s"] = s
+    return out
+
+
+class BatchHandle(Handle):
+    """Handle of a batch (pdhcg_setup with count > 1)."""
+
+    def __init__(self, ptr, probs, settings):
+        self.ptr = ptr
+        self.ns = [int(p.n) for p in probs]
+        self.ms = [int(p.m) for p in probs]
+        self.count = len(probs)
+        self.settings = settings
+
+    def _dims(self, inst):
+        return self.ns[inst], self.ms[inst]
+
+    def solve(self, x0s=None, y0s=None, want_s=False):
+        """pdhcg_solve_batch: one persistent launch for every instance.
+        x0s / y0s: None or sequences of per-instance arrays (or None)."""
+        lib = load()
+        res = (ResultC * self.count)()
+        xs = [np.zeros(n) for n in self.ns]
+        ys = [np.zeros(m) for m in self.ms]
+        ss = [np.zeros(n) for n in self.ns] if want_s else [None] * self.count
+        for i in range(self.count):
+            res[i].x = _ptr(xs[i], C.c_double)
+            res[i].y = _ptr(ys[i], C.c_double)
+            res[i].s = _ptr(ss[i], C.c_double) if want_s else None
+        keep = []
+
+        def ptr_array(vs):
+            if vs is None:
+                return None
+            arr = (_dp * self.count)()
+            for i, v in enumerate(vs):
+                if v is not None:
+                    a = np.ascontiguousarray(v, dtype=np.float64)
+                    keep.append(a)
+                    arr[i] = _ptr(a, C.c_double)
+            return arr
+
+        _check(lib.pdhcg_solve_batch(self.ptr, ptr_array(x0s), ptr_array(y0s), res),
+               "pdhcg_solve_batch")
+        return [_result_dict(res[i], xs[i], ys[i], ss[i]) for i in range(self.count)]
+
+
+def setup_batch(probs, settings=None, **kw) -> BatchHandle:
+    """pdhcg_setup with count = len(probs) > 1."""
+    lib = load()
+    probs = list(probs)
+    if len(probs) < 2:
+        raise ValueError("a batch needs at least two problems; use setup() for one")
+    s = settings if settings is not None else default_settings(**kw)
+    ms = [_Marshalled(p) for p in probs]
+    arr = (ProblemC * len(probs))(*[m.pc for m in ms])
+    h = C.c_void_p()
+    _check(lib.pdhcg_setup(arr, len(probs), C.byref(s), C.byref(h)), "pdhcg_setup")
+    return BatchHandle(h.value, probs, s)
 
 
 def setup(prob, settings=None, **kw) -> Handle:

@@ -63,6 +63,8 @@ struct Instance {
   long n_warm = 0;
 };
 
+struct Batch;
+
 struct Handle {
   pdhcg_settings s;
   DevSettings ds;
@@ -70,6 +72,38 @@ struct Handle {
   hipStream_t stream = nullptr;
   double setup_s = 0.0;
   unsigned long long spin_limit = 0;
+  int rate_khz = 100000;
+  Batch* B = nullptr;     // count > 1: the batch arena and its launch state
+};
+
+// Batch of independent instances.  All instance data lives in one device
+// arena, each instance in a contiguous 256-byte aligned region; the
+// descriptors (device pointers into the arena, step sizes, lane mapping) are
+// an array the batch kernel indexes by instance.
+struct Batch {
+  int count = 0;
+  DevBuf mem;
+  char* arena = nullptr;
+  std::vector<InstDesc> desc;
+  InstDesc* d_desc = nullptr;
+  int* d_queue = nullptr;
+  int* d_order = nullptr;
+  Ctl* d_ctl = nullptr;
+  long* d_offx = nullptr;
+  long* d_offy = nullptr;
+  double* d_outx = nullptr;
+  double* d_outy = nullptr;
+  double* d_x0 = nullptr;
+  double* d_y0 = nullptr;
+  double* d_norm = nullptr;
+  std::vector<long> offx, offy;   // count + 1 prefix sums of n and m
+  int grid = 1;
+  bool cones = false;             // some instance has SOC/RSOC/EXP/POW blocks
+  int div_a = 2, div_at = 2;      // lanes-per-row rule: lanes <= mean nnz / div
+  double tune_s = 0.0;
+  hipStream_t cap = nullptr;      // private stream used for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 int pow2_floor(double v) {
@@ -143,6 +177,14 @@ int upload_instance(Handle* h, Instance* I) {
   }
   P.R = H.r > 0 ? B.upload(H.R) : nullptr;
   P.Dm = H.r > 0 ? B.upload(H.D) : nullptr;
+  P.A_valf = P.AT_valf = P.P_valf = P.Rf = nullptr;
+  if (h->s.precision == PDHCG_PREC_FP32) {
+    auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+    P.A_valf = B.upload(f32(H.A.val));
+    P.AT_valf = B.upload(f32(H.AT.val));
+    if (H.P.rows > 0) P.P_valf = B.upload(f32(H.P.val));
+    if (H.r > 0) P.Rf = B.upload(f32(H.R));
+  }
   P.b = B.upload(H.b);
   P.c = B.upload(H.c);
   P.qd = B.upload(H.qdiag);
@@ -330,6 +372,408 @@ void free_instance(Instance* I) {
   delete I;
 }
 
+// per-workgroup phase timers (settings.verbose & 8): summary on stderr, and
+// one CSV line per workgroup into $PDHCG_PROFILE_DUMP when set
+void report_phases(const unsigned long long* dpt, int grid) {
+  static const char* names[PT_COUNT] = {"init", "P1", "P2", "P3", "P4", "P6", "check",
+                                        "halpern", "barrier", "proj", "wcall", "ncall"};
+  int dev = 0, khz = 100000;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  std::vector<unsigned long long> pt((size_t)PT_COUNT * grid);
+  (void)hipMemcpy(pt.data(), dpt, pt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+  std::fprintf(stderr, "pdhcg phase times over %d workgroups: mean / max / argmax [ms]\n", grid);
+  for (int i = 0; i < PT_COUNT; ++i) {
+    double s = 0, mx = 0;
+    int am = 0;
+    for (int w = 0; w < grid; ++w) {
+      double v = pt[(size_t)w * PT_COUNT + i] / (double)khz;
+      s += v;
+      if (v > mx) { mx = v; am = w; }
+    }
+    std::fprintf(stderr, "  %-8s %10.3f %10.3f %5d\n", names[i], s / grid, mx, am);
+  }
+  if (const char* path = std::getenv("PDHCG_PROFILE_DUMP")) {
+    if (FILE* f = std::fopen(path, "w")) {
+      for (int w = 0; w < grid; ++w) {
+        std::fprintf(f, "%d", w);
+        for (int i = 0; i < PT_COUNT; ++i) std::fprintf(f, ",%.4f", pt[(size_t)w * PT_COUNT + i] / (double)khz);
+        std::fprintf(f, "\n");
+      }
+      std::fclose(f);
+    }
+  }
+}
+
+// unscaled outputs and counters of one solved instance
+void finish_result(const HostInstance& H, const Ctl& c, int status, const double* wx, const double* wy,
+                   double eta, double setup_s, pdhcg_result* res) {
+  const long n = H.n, m = H.m;
+  res->status = status;
+  res->iterations = c.ktot;
+  res->inner_iterations = c.inner_total;
+  res->restarts = c.restarts;
+  res->rel_primal = c.rel_p;
+  res->rel_dual = c.rel_d;
+  res->rel_gap = c.rel_gap;
+  res->primal_obj = c.pobj;
+  res->dual_obj = c.dobj;
+  res->omega = c.omega;
+  res->a_norm = 0.998 / eta;
+  res->setup_s = setup_s;
+  if (res->x)
+    for (long i = 0; i < n; ++i) res->x[i] = H.nu_b * wx[i] / H.Sx[i];
+  if (res->y)
+    for (long l = 0; l < m; ++l) res->y[l] = H.nu_c * H.Sy[l] * wy[l];
+  if (res->s) {
+    // s = nu_c S_x (Q^ w + c^ - A^T w_y)
+    std::vector<double> q(n, 0.0);
+    if (H.P.rows > 0)
+      for (long i = 0; i < n; ++i)
+        for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) q[i] += H.P.val[k] * wx[H.P.col[k]];
+    if (H.r > 0) {
+      std::vector<double> hh(H.r, 0.0), ht(H.r, 0.0);
+      for (int k = 0; k < H.r; ++k)
+        for (long i = 0; i < n; ++i) hh[k] += H.R[(size_t)k * n + i] * wx[i];
+      for (int k = 0; k < H.r; ++k)
+        for (int b = 0; b < H.r; ++b) ht[k] += H.D[k * H.r + b] * hh[b];
+      for (long i = 0; i < n; ++i)
+        for (int k = 0; k < H.r; ++k) q[i] += H.R[(size_t)k * n + i] * ht[k];
+    }
+    for (long i = 0; i < n; ++i) {
+      double aty = 0.0;
+      for (int64_t k = H.AT.ptr[i]; k < H.AT.ptr[i + 1]; ++k) aty += H.AT.val[k] * wy[H.AT.col[k]];
+      res->s[i] = H.nu_c * H.Sx[i] * (q[i] + H.c[i] - aty);
+    }
+  }
+}
+
+// carves one instance's region of the batch arena: `put` places a host
+// array (copied into the staging image when there is one), `take` reserves
+// device space; offsets are 256-byte aligned
+struct Carve {
+  size_t off = 0;
+  char* stage = nullptr;      // host image of the region (null: sizing pass)
+  uintptr_t dev = 0;          // device address of the region
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(dev + off);
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+  template <class T>
+  T* put(const std::vector<T>& v) {
+    const size_t o = (off + 255) & ~(size_t)255;
+    T* p = take<T>(v.size());
+    if (stage && !v.empty()) std::memcpy(stage + o, v.data(), v.size() * sizeof(T));
+    return p;
+  }
+};
+
+void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D) {
+  const long n = H.n, m = H.m;
+  DevProblem& P = D.P;
+  P = DevProblem{};
+  P.n = H.n;
+  P.m = H.m;
+  P.r = H.r;
+  P.A_ptr = c.put(H.A.ptr);
+  P.A_col = c.put(H.A.col);
+  P.A_val = c.put(H.A.val);
+  P.AT_ptr = c.put(H.AT.ptr);
+  P.AT_col = c.put(H.AT.col);
+  P.AT_val = c.put(H.AT.val);
+  if (H.P.rows > 0) {
+    P.P_ptr = c.put(H.P.ptr);
+    P.P_col = c.put(H.P.col);
+    P.P_val = c.put(H.P.val);
+  }
+  P.R = H.r > 0 ? c.put(H.R) : nullptr;
+  P.Dm = H.r > 0 ? c.put(H.D) : nullptr;
+  P.b = c.put(H.b);
+  P.c = c.put(H.c);
+  P.qd = c.put(H.qdiag);
+  P.Sx = c.put(H.Sx);
+  P.Sy = c.put(H.Sy);
+  P.ctype = c.put(H.ctype);
+  P.n_wave = (int)H.wave_start.size();
+  P.n_lane = (int)H.lane_start.size();
+  P.wave_start = c.put(H.wave_start);
+  P.wave_dim = c.put(H.wave_dim);
+  P.wave_type = c.put(H.wave_type);
+  P.wave_euclid = c.put(H.wave_euclid);
+  P.lane_start = c.put(H.lane_start);
+  P.lane_type = c.put(H.lane_type);
+  P.lane_alpha = c.put(H.lane_alpha);
+  P.lane_euclid = c.put(H.lane_euclid);
+  P.nu_b = H.nu_b;
+  P.nu_c = H.nu_c;
+  P.norm_b = H.norm_b;
+  P.norm_c = H.norm_c;
+  P.q_diag = H.q_diag ? 1 : 0;
+  DevVec& V = D.V;
+  V = DevVec{};
+  V.x = c.take<double>(n);
+  V.y = c.take<double>(m);
+  V.ax = c.take<double>(n);
+  V.ay = c.take<double>(m);
+  V.wx = c.take<double>(n);
+  V.wy = c.take<double>(m);
+  V.Ax = c.take<double>(m);
+  V.Aa = c.take<double>(m);
+  V.Aw = c.take<double>(m);
+  V.v = c.take<double>(n);
+  V.u = c.take<double>(n);
+  V.up = c.take<double>(n);
+  V.g = c.take<double>(n);
+  V.gp = c.take<double>(n);
+  V.zb = c.take<double>(n);
+  V.s = c.take<double>(n);
+  V.t1 = c.take<double>(n);
+  V.t2 = c.take<double>(n);
+  D.n_warm = 2 * (P.n_wave + P.n_lane);
+  V.warm = c.take<double>(D.n_warm);
+  V.partials = c.take<double>(SL_COUNT);
+  D.T = TraceBufs{};
+  if (trace_cap > 0) {
+    D.T.cap = trace_cap;
+    D.T.x = c.take<double>((size_t)trace_cap * n);
+    D.T.wx = c.take<double>((size_t)trace_cap * n);
+    D.T.y = c.take<double>((size_t)trace_cap * std::max<long>(m, 1));
+    D.T.wy = c.take<double>((size_t)trace_cap * std::max<long>(m, 1));
+    D.T.sc = c.take<double>((size_t)trace_cap * 8);
+  }
+  D.qmax = 0.0;
+  for (double q : H.qdiag) D.qmax = std::max(D.qmax, q);
+  int maxdim = 1;
+  for (int d : H.wave_dim) maxdim = std::max(maxdim, d);
+  D.lg = maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64);
+  D.x0 = nullptr;
+  D.y0 = nullptr;
+}
+
+// lanes per row for rows of mean length `mean`: a power of two <= mean/div
+int lanes_rule(double mean, int div) {
+  int L = 1;
+  while (L * 2 <= std::max(1.0, mean / div) && L < 64) L *= 2;
+  return L;
+}
+
+void set_lanes(Handle* h, int div_a, int div_at) {
+  Batch* B = h->B;
+  for (int i = 0; i < B->count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    int64_t nz_at = H.AT.nnz();
+    if (H.P.rows > 0) nz_at = std::max<int64_t>(nz_at, H.P.nnz());
+    const double mat = H.n > 0 ? (double)nz_at / H.n : 1.0;
+    const double ma = H.m > 0 ? (double)H.A.nnz() / H.m : 1.0;
+    B->desc[i].la = h->s.lanes_at > 0 ? h->s.lanes_at : lanes_rule(mat, div_at);
+    B->desc[i].lr = h->s.lanes_a > 0 ? h->s.lanes_a : lanes_rule(ma, div_a);
+  }
+  B->div_a = div_a;
+  B->div_at = div_at;
+}
+
+int upload_desc(Handle* h, hipStream_t st) {
+  Batch* B = h->B;
+  HIPCHK(hipMemcpyAsync(B->d_desc, B->desc.data(), sizeof(InstDesc) * B->count, hipMemcpyHostToDevice, st));
+  return PDHCG_OK;
+}
+
+BatchArgs batch_args(Handle* h, long long stop_at) {
+  Batch* B = h->B;
+  BatchArgs a{};
+  a.desc = B->d_desc;
+  a.count = B->count;
+  a.order = B->d_order;
+  a.queue = B->d_queue;
+  a.S = h->ds;
+  a.stop_at = stop_at;
+  const double lim = h->s.time_limit;
+  a.limit_ticks = (lim > 0 && lim < 1e9) ? (unsigned long long)(lim * 1e3 * h->rate_khz) : 0ull;
+  return a;
+}
+
+int setup_batch(Handle* h) {
+  Batch* B = h->B;
+  const int count = B->count;
+  const int cap = h->s.trace_iters;
+  hipStream_t st = h->stream;
+  B->desc.assign(count, InstDesc{});
+  // region sizes, then one arena, then the staged images in chunks
+  std::vector<size_t> base(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    Carve c;
+    InstDesc tmp{};
+    carve_instance(h->inst[i]->H, cap, c, tmp);
+    base[i + 1] = base[i] + ((c.off + 255) & ~(size_t)255);
+  }
+  B->arena = B->mem.alloc<char>(base[count]);
+  if (B->mem.err != hipSuccess) return B->mem.err == hipErrorOutOfMemory ? PDHCG_E_MEM : PDHCG_E_HIP;
+  {
+    std::vector<char> stage;
+    int first = 0;
+    const size_t chunk = (size_t)64 << 20;
+    auto flush = [&](int upto) -> int {
+      if (stage.empty()) return PDHCG_OK;
+      HIPCHK(hipMemcpy(B->arena + base[first], stage.data(), stage.size(), hipMemcpyHostToDevice));
+      stage.clear();
+      first = upto;
+      return PDHCG_OK;
+    };
+    for (int i = 0; i < count; ++i) {
+      const size_t sz = base[i + 1] - base[i];
+      if (!stage.empty() && stage.size() + sz > chunk) {
+        int rc = flush(i);
+        if (rc != PDHCG_OK) return rc;
+      }
+      const size_t o = stage.size();
+      stage.resize(o + sz, 0);
+      Carve c;
+      c.stage = stage.data() + o;
+      c.dev = (uintptr_t)(B->arena + base[i]);
+      carve_instance(h->inst[i]->H, cap, c, B->desc[i]);
+    }
+    int rc = flush(count);
+    if (rc != PDHCG_OK) return rc;
+  }
+  // control blocks, queue, order (largest first), packed outputs
+  B->d_ctl = B->mem.alloc<Ctl>(count);
+  B->d_desc = B->mem.alloc<InstDesc>(count);
+  B->d_queue = B->mem.alloc<int>(1);
+  B->d_norm = B->mem.alloc<double>(count);
+  B->offx.assign(count + 1, 0);
+  B->offy.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    B->offx[i + 1] = B->offx[i] + h->inst[i]->H.n;
+    B->offy[i + 1] = B->offy[i] + h->inst[i]->H.m;
+    B->desc[i].ctl = B->d_ctl + i;
+  }
+  B->d_offx = B->mem.upload(B->offx);
+  B->d_offy = B->mem.upload(B->offy);
+  B->d_outx = B->mem.alloc<double>(B->offx[count]);
+  B->d_outy = B->mem.alloc<double>(B->offy[count]);
+  std::vector<int> order(count);
+  std::vector<double> work(count);
+  for (int i = 0; i < count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    order[i] = i;
+    work[i] = (double)H.n * (4.0 + H.r) + 2.0 * (double)H.A.nnz() + (double)H.P.nnz() +
+              32.0 * (double)(H.wave_start.size() + H.lane_start.size());
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  B->d_order = B->mem.upload(order);
+  if (B->mem.err != hipSuccess) return B->mem.err == hipErrorOutOfMemory ? PDHCG_E_MEM : PDHCG_E_HIP;
+  for (int i = 0; i < count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    if (!H.wave_start.empty() || !H.lane_start.empty()) B->cones = true;
+  }
+  const int lim = batch_grid_limit(B->cones);
+  B->grid = h->s.grid_dim > 0 ? std::min(h->s.grid_dim, lim) : lim;
+  B->grid = std::max(1, std::min(B->grid, count));
+
+  // step sizes: power iteration per instance with the fixed lane rule
+  set_lanes(h, 2, 2);
+  int rc = upload_desc(h, st);
+  if (rc != PDHCG_OK) return rc;
+  std::vector<double> an(count, h->s.a_norm);
+  if (!(h->s.a_norm > 0)) {
+    HIPCHK(launch_batch_power(B->d_desc, count, h->s.power_iters, B->d_norm, st));
+    HIPCHK(hipMemcpyAsync(an.data(), B->d_norm, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int i = 0; i < count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    double a_n = an[i];
+    if (!(a_n > 0)) a_n = 1.0;
+    B->desc[i].P.eta = 0.998 / a_n;
+    double nb = 0, nc = 0;
+    for (double v : H.b) nb += v * v;
+    for (double v : H.c) nc += v * v;
+    nb = std::sqrt(nb);
+    nc = std::sqrt(nc);
+    B->desc[i].P.omega0 = h->s.omega0 > 0 ? h->s.omega0 : ((nb > 1e-10 && nc > 1e-10) ? nc / nb : 1.0);
+    h->inst[i]->P = B->desc[i].P;
+  }
+  // autotuner: time a fixed number of outer iterations of the whole batch
+  // under each candidate lanes-per-row rule and keep the fastest
+  if (h->s.autotune && h->s.lanes_a <= 0 && h->s.lanes_at <= 0) {
+    const double t0 = now_s();
+    const int it = h->s.tune_iters > 0 ? h->s.tune_iters : 64;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 3.4e38f;
+    int bda = 2, bdat = 2;
+    const int divs_a[] = {1, 2, 4, 8, 16};
+    const int divs_at[] = {1, 2, 4};
+    for (int pass = 0; pass < 2; ++pass) {     // pass 0 warms caches and code
+      for (int da : divs_a) {
+        for (int dat : divs_at) {
+          set_lanes(h, da, dat);
+          rc = upload_desc(h, st);
+          if (rc != PDHCG_OK) return rc;
+          HIPCHK(launch_batch_reset(B->d_desc, count, B->d_queue, st));
+          HIPCHK(hipEventRecord(e0, st));
+          HIPCHK(launch_batch(batch_args(h, it), B->cones, B->grid, st));
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (pass == 1 && ms < best) {
+            best = ms;
+            bda = da;
+            bdat = dat;
+          }
+          if (pass == 0) break;
+        }
+        if (pass == 0) break;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_lanes(h, bda, bdat);
+    B->tune_s = now_s() - t0;
+    if (h->s.verbose)
+      std::fprintf(stderr, "pdhcg: batch autotune: lanes rule A/%d, A^T/%d (%.3f ms per probe)\n", bda, bdat,
+                   best);
+  }
+  rc = upload_desc(h, st);
+  if (rc != PDHCG_OK) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  return PDHCG_OK;
+}
+
+int capture_batch(Handle* h) {
+  Batch* B = h->B;
+  if (B->exec) return PDHCG_OK;
+  if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_batch_reset(B->d_desc, B->count, B->d_queue, B->cap);
+  if (e == hipSuccess) e = launch_batch(batch_args(h, h->s.max_iter), B->cones, B->grid, B->cap);
+  if (e == hipSuccess)
+    e = launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy, B->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return PDHCG_E_HIP;
+  }
+  B->graph = g;
+  HIPCHK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+  return PDHCG_OK;
+}
+
+void free_batch(Batch* B) {
+  if (!B) return;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  B->mem.release();
+  delete B;
+}
+
 }  // namespace
 
 extern "C" {
@@ -370,6 +814,10 @@ int pdhcg_default_settings(pdhcg_settings* s) {
   s->host_poll = 512;
   s->stream = nullptr;
   s->verbose = 0;
+  s->time_kernels = 0;
+  s->autotune = 1;
+  s->tune_iters = 64;
+  s->fp32_tol = 0.0;
   return PDHCG_OK;
 }
 
@@ -400,11 +848,11 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   if (!out) return PDHCG_E_ARG;
   *out = nullptr;
   if (!probs || !s || count < 1) return PDHCG_E_ARG;
-  if (count != 1) return PDHCG_E_ARG;   // batches: pdhcg_solve_batch
   if (s->tol <= 0 || s->check_every < 1 || s->j_max < 1 || s->max_iter < 0 ||
       !(s->rho >= 0.5 && s->rho <= 1.0) || s->power_iters < 0 || s->scheme != PDHCG_SCHEME_RH ||
-      s->precision != PDHCG_PREC_FP64 || s->trace_iters < 0)
+      (s->precision != PDHCG_PREC_FP64 && s->precision != PDHCG_PREC_FP32) || s->trace_iters < 0)
     return PDHCG_E_ARG;
+  if (count > 1 && s->precision != PDHCG_PREC_FP64) return PDHCG_E_ARG;   // batches are FP64
   if (s->lanes_at < 0 || s->lanes_at > 64 || (s->lanes_at & (s->lanes_at - 1)) ||
       s->lanes_a < 0 || s->lanes_a > 64 || (s->lanes_a & (s->lanes_a - 1)))
     return PDHCG_E_ARG;
@@ -431,7 +879,18 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
     return PDHCG_E_HIP;
   }
   if (rate_khz <= 0) rate_khz = 100000;
+  h->rate_khz = rate_khz;
   h->spin_limit = (unsigned long long)rate_khz * 1000ull * 4ull;   // 4 s
+  if (count > 1) {
+    h->B = new (std::nothrow) Batch();
+    if (!h->B) { pdhcg_free(h); return PDHCG_E_MEM; }
+    h->B->count = count;
+    int rc = setup_batch(h);
+    if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
+    h->setup_s = now_s() - t0;
+    *out = h;
+    return PDHCG_OK;
+  }
   for (int i = 0; i < count; ++i) {
     Instance* I = h->inst[i];
     int rc = upload_instance(h, I);
@@ -458,7 +917,7 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
 int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res) {
   Handle* h = (Handle*)hv;
   if (!h || !res) return PDHCG_E_ARG;
-  if (h->inst.size() != 1) return PDHCG_E_STATE;
+  if (h->inst.size() != 1 || h->B) return PDHCG_E_STATE;
   Instance* I = h->inst[0];
   const HostInstance& H = I->H;
   const long n = H.n, m = H.m;
@@ -505,6 +964,13 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   Ctl c = c0;
   int status = 0;
   const long long maxit = h->s.max_iter;
+  // FP32 mode: FP32 bulk sweeps until the looser tolerance fp32_tol, then an
+  // FP64 polish restarted at that candidate (same primal weight, inner
+  // tolerance and counters) down to tol
+  bool phase32 = h->s.precision == PDHCG_PREC_FP32;
+  const double tol32 = std::max(h->s.tol, h->s.fp32_tol > 0 ? h->s.fp32_tol : 10.0 * h->s.tol);
+  if (phase32) a.S.tol = tol32;
+  long long switch_at = -1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   const bool timing = h->s.time_kernels != 0;
   double ksum = 0.0;
@@ -516,7 +982,7 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   while (true) {
     a.stop_at = std::min<long long>(maxit, c.ktot + h->s.host_poll);
     if (timing) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_solve(a, I->grid, st));
+    HIPCHK(launch_solve(a, phase32, I->grid, st));
     if (timing) HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(hipMemcpyAsync(&c, I->ctl, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -525,6 +991,23 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
       ksum += ms * 1e-3;
+    }
+    if (c.status == PDHCG_OPTIMAL && phase32 && tol32 > h->s.tol) {
+      // precision switch: the FP64 run re-initialises from (zb, y) = the
+      // FP32 phase's candidate (w_x, w_y)
+      const double* Wd = I->P.q_diag ? I->V.wx : I->V.u;
+      HIPCHK(hipMemcpyAsync(I->V.zb, Wd, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if (m > 0) HIPCHK(hipMemcpyAsync(I->V.y, I->V.wy, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+      c.status = 0;
+      c.started = 0;
+      c.resume = 1;
+      HIPCHK(hipMemcpyAsync(I->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      phase32 = false;
+      a.S.tol = h->s.tol;
+      switch_at = c.ktot;
+      if (c.ktot >= maxit) { status = PDHCG_MAX_ITER; break; }
+      continue;
     }
     if (c.status != 0) { status = c.status; break; }
     if (c.ktot >= maxit) { status = PDHCG_MAX_ITER; break; }
@@ -538,37 +1021,10 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   res->kernel_launches = nlaunch;
   res->grid_dim = I->grid;
   res->block_dim = block_size();
+  res->polish_iterations = switch_at >= 0 ? c.ktot - switch_at : 0;
   if (h->s.verbose & 8) {
-    static const char* names[PT_COUNT] = {"init", "P1", "P2", "P3", "P4", "P6", "check",
-                                          "halpern", "barrier", "proj", "wcall", "ncall"};
-    int dev = 0, khz = 100000;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-    std::vector<unsigned long long> pt((size_t)PT_COUNT * I->grid);
-    (void)hipMemcpy(pt.data(), dpt, pt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    report_phases(dpt, I->grid);
     (void)hipFree(dpt);
-    std::fprintf(stderr, "pdhcg phase times over %d workgroups (lanes at=%d a=%d): mean / max / argmax [ms]\n",
-                 I->grid, I->P.at_lanes, I->P.a_lanes);
-    for (int i = 0; i < PT_COUNT; ++i) {
-      double s = 0, mx = 0;
-      int am = 0;
-      for (int w = 0; w < I->grid; ++w) {
-        double v = pt[(size_t)w * PT_COUNT + i] / (double)khz;
-        s += v;
-        if (v > mx) { mx = v; am = w; }
-      }
-      std::fprintf(stderr, "  %-8s %10.3f %10.3f %5d\n", names[i], s / I->grid, mx, am);
-    }
-    if (const char* path = std::getenv("PDHCG_PROFILE_DUMP")) {
-      if (FILE* f = std::fopen(path, "w")) {
-        for (int w = 0; w < I->grid; ++w) {
-          std::fprintf(f, "%d,%ld,%ld", w, (long)0, (long)0);
-          for (int i = 0; i < PT_COUNT; ++i) std::fprintf(f, ",%.4f", pt[(size_t)w * PT_COUNT + i] / (double)khz);
-          std::fprintf(f, "\n");
-        }
-        std::fclose(f);
-      }
-    }
   }
   // results (unscaled)
   const double* W = I->P.q_diag ? I->V.wx : I->V.u;
@@ -578,71 +1034,139 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
     if (m > 0) HIPCHK(hipMemcpyAsync(wy.data(), I->V.wy, m * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
-  res->status = status;
-  res->iterations = c.ktot;
-  res->inner_iterations = c.inner_total;
-  res->restarts = c.restarts;
-  res->rel_primal = c.rel_p;
-  res->rel_dual = c.rel_d;
-  res->rel_gap = c.rel_gap;
-  res->primal_obj = c.pobj;
-  res->dual_obj = c.dobj;
-  res->omega = c.omega;
-  res->a_norm = 0.998 / I->P.eta;
-  res->setup_s = h->setup_s;
-  if (res->x)
-    for (long i = 0; i < n; ++i) res->x[i] = H.nu_b * wx[i] / H.Sx[i];
-  if (res->y)
-    for (long l = 0; l < m; ++l) res->y[l] = H.nu_c * H.Sy[l] * wy[l];
-  if (res->s) {
-    // s = nu_c S_x (Q^ w + c^ - A^T w_y)
-    std::vector<double> q(n, 0.0);
-    if (H.P.rows > 0)
-      for (long i = 0; i < n; ++i)
-        for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) q[i] += H.P.val[k] * wx[H.P.col[k]];
-    if (H.r > 0) {
-      std::vector<double> hh(H.r, 0.0), ht(H.r, 0.0);
-      for (int k = 0; k < H.r; ++k)
-        for (long i = 0; i < n; ++i) hh[k] += H.R[(size_t)k * n + i] * wx[i];
-      for (int k = 0; k < H.r; ++k)
-        for (int b = 0; b < H.r; ++b) ht[k] += H.D[k * H.r + b] * hh[b];
-      for (long i = 0; i < n; ++i)
-        for (int k = 0; k < H.r; ++k) q[i] += H.R[(size_t)k * n + i] * ht[k];
-    }
-    for (long i = 0; i < n; ++i) {
-      double aty = 0.0;
-      for (int64_t k = H.AT.ptr[i]; k < H.AT.ptr[i + 1]; ++k) aty += H.AT.val[k] * wy[H.AT.col[k]];
-      res->s[i] = H.nu_c * H.Sx[i] * (q[i] + H.c[i] - aty);
-    }
-  }
+  finish_result(H, c, status, wx.data(), wy.data(), I->P.eta, h->setup_s, res);
   res->solve_s = now_s() - t0;
   return PDHCG_OK;
 }
 
 int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y0s, pdhcg_result* res) {
-  (void)hv; (void)x0s; (void)y0s; (void)res;
-  return PDHCG_E_STATE;
+  Handle* h = (Handle*)hv;
+  if (!h || !res) return PDHCG_E_ARG;
+  if (!h->B) return pdhcg_solve(hv, x0s ? x0s[0] : nullptr, y0s ? y0s[0] : nullptr, res);
+  Batch* B = h->B;
+  const int count = B->count;
+  hipStream_t st = h->stream;
+  const double t0 = now_s();
+  // warm starts: scaled on the host into packed buffers; the reset node of
+  // the graph copies them into each instance's zb / y
+  bool dirty = false;
+  std::vector<double> px, py;
+  if (x0s) px.assign(std::max<long>(B->offx[count], 1), 0.0);
+  if (y0s) py.assign(std::max<long>(B->offy[count], 1), 0.0);
+  if (x0s && !B->d_x0) B->d_x0 = B->mem.alloc<double>(B->offx[count]);
+  if (y0s && !B->d_y0) B->d_y0 = B->mem.alloc<double>(std::max<long>(B->offy[count], 1));
+  if (B->mem.err != hipSuccess) return PDHCG_E_MEM;
+  for (int i = 0; i < count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    const double* x0 = x0s ? x0s[i] : nullptr;
+    const double* y0 = y0s ? y0s[i] : nullptr;
+    if (x0)
+      for (long j = 0; j < H.n; ++j) px[B->offx[i] + j] = H.Sx[j] * x0[j] / H.nu_b;
+    if (y0)
+      for (long l = 0; l < H.m; ++l) py[B->offy[i] + l] = y0[l] / (H.nu_c * H.Sy[l]);
+    const double* want_x = x0 ? B->d_x0 + B->offx[i] : nullptr;
+    const double* want_y = (y0 && H.m > 0) ? B->d_y0 + B->offy[i] : nullptr;
+    if (B->desc[i].x0 != want_x || B->desc[i].y0 != want_y) {
+      B->desc[i].x0 = want_x;
+      B->desc[i].y0 = want_y;
+      dirty = true;
+    }
+  }
+  if (x0s) HIPCHK(hipMemcpyAsync(B->d_x0, px.data(), sizeof(double) * B->offx[count], hipMemcpyHostToDevice, st));
+  if (y0s && B->offy[count] > 0)
+    HIPCHK(hipMemcpyAsync(B->d_y0, py.data(), sizeof(double) * B->offy[count], hipMemcpyHostToDevice, st));
+  if (dirty) {
+    int rc = upload_desc(h, st);
+    if (rc != PDHCG_OK) return rc;
+  }
+  int rc = capture_batch(h);
+  if (rc != PDHCG_OK) return rc;
+  const bool timing = h->s.time_kernels != 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (timing) {
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    HIPCHK(hipEventRecord(ev0, st));
+  }
+  unsigned long long* dpt = nullptr;
+  if (h->s.verbose & 8) {
+    // profiled run: a direct launch with phase timers instead of the graph
+    HIPCHK(hipMalloc(&dpt, sizeof(unsigned long long) * PT_COUNT * B->grid));
+    BatchArgs pa = batch_args(h, h->s.max_iter);
+    pa.ptimes = dpt;
+    HIPCHK(launch_batch_reset(B->d_desc, B->count, B->d_queue, st));
+    HIPCHK(launch_batch(pa, B->cones, B->grid, st));
+    HIPCHK(launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy, st));
+  } else {
+    HIPCHK(hipGraphLaunch(B->exec, st));
+  }
+  if (timing) HIPCHK(hipEventRecord(ev1, st));
+  std::vector<Ctl> ctl(count);
+  std::vector<double> ox(std::max<long>(B->offx[count], 1)), oy(std::max<long>(B->offy[count], 1));
+  HIPCHK(hipMemcpyAsync(ctl.data(), B->d_ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ox.data(), B->d_outx, sizeof(double) * B->offx[count], hipMemcpyDeviceToHost, st));
+  if (B->offy[count] > 0)
+    HIPCHK(hipMemcpyAsync(oy.data(), B->d_outy, sizeof(double) * B->offy[count], hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double ks = 0.0;
+  if (timing) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+    ks = ms * 1e-3;
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+  }
+  if (dpt) {
+    report_phases(dpt, B->grid);
+    (void)hipFree(dpt);
+  }
+  std::vector<double> zx, zy;
+  for (int i = 0; i < count; ++i) {
+    const HostInstance& H = h->inst[i]->H;
+    const Ctl& c = ctl[i];
+    int status = c.status;
+    if (status == 0) status = c.ktot >= h->s.max_iter ? PDHCG_MAX_ITER : PDHCG_TIME_LIMIT;
+    const double* wx = ox.data() + B->offx[i];
+    const double* wy = oy.data() + B->offy[i];
+    if (c.ktot == 0) {
+      zx.assign(std::max(H.n, 1), 0.0);
+      zy.assign(std::max(H.m, 1), 0.0);
+      wx = zx.data();
+      wy = zy.data();
+    }
+    finish_result(H, c, status, wx, wy, B->desc[i].P.eta, h->setup_s, &res[i]);
+    res[i].kernel_s = i == 0 ? ks : 0.0;
+    res[i].kernel_launches = i == 0 ? 1 : 0;
+    res[i].grid_dim = B->grid;
+    res[i].block_dim = block_size();
+  }
+  const double dt = now_s() - t0;
+  for (int i = 0; i < count; ++i) res[i].solve_s = dt;
+  return PDHCG_OK;
 }
+
 
 int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {
   Handle* h = (Handle*)hv;
   if (!h || !t || inst < 0 || inst >= (int)h->inst.size()) return PDHCG_E_ARG;
   Instance* I = h->inst[inst];
-  if (I->T.cap <= 0) return PDHCG_E_NOTRACE;
+  const TraceBufs& T = h->B ? h->B->desc[inst].T : I->T;
+  const Ctl* dctl = h->B ? h->B->desc[inst].ctl : I->ctl;
+  if (T.cap <= 0) return PDHCG_E_NOTRACE;
   Ctl c;
-  if (hipMemcpy(&c, I->ctl, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return PDHCG_E_HIP;
-  long rec = std::min<long long>(c.ktot, I->T.cap);
+  if (hipMemcpy(&c, dctl, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return PDHCG_E_HIP;
+  long rec = std::min<long long>(c.ktot, T.cap);
   rec = std::min<long>(rec, t->count);
   const long n = I->H.n, m = I->H.m;
   auto cp = [&](double* dst, const double* src, size_t cnt) -> bool {
     if (!dst || cnt == 0) return true;
     return hipMemcpy(dst, src, cnt * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
   };
-  if (!cp(t->x, I->T.x, rec * n) || !cp(t->wx, I->T.wx, rec * n) || !cp(t->y, I->T.y, rec * m) ||
-      !cp(t->wy, I->T.wy, rec * m))
+  if (!cp(t->x, T.x, rec * n) || !cp(t->wx, T.wx, rec * n) || !cp(t->y, T.y, rec * m) ||
+      !cp(t->wy, T.wy, rec * m))
     return PDHCG_E_HIP;
   std::vector<double> sc(rec * 8);
-  if (!cp(sc.data(), I->T.sc, rec * 8)) return PDHCG_E_HIP;
+  if (!cp(sc.data(), T.sc, rec * 8)) return PDHCG_E_HIP;
   for (long k = 0; k < rec; ++k) {
     if (t->tau) t->tau[k] = sc[k * 8 + 0];
     if (t->sigma) t->sigma[k] = sc[k * 8 + 1];
@@ -674,6 +1198,7 @@ int pdhcg_get_scaling(void* hv, int32_t inst, double* Sx, double* Sy, double* nu
 void pdhcg_free(void* hv) {
   Handle* h = (Handle*)hv;
   if (!h) return;
+  free_batch(h->B);
   for (Instance* I : h->inst) free_instance(I);
   delete h;
 }

@@ -42,6 +42,8 @@ struct DevProblem {
   const int64_t* AT_ptr; const int* AT_col; const double* AT_val;
   const int64_t* P_ptr;  const int* P_col;  const double* P_val;  // nullable
   const double* R;       // r x n row-major (scaled)
+  // FP32 copies of the values of A, A^T, P, R (FP32 mode only; else null)
+  const float* A_valf; const float* AT_valf; const float* P_valf; const float* Rf;
   const double* Dm;      // r x r (scaled)
   const double* b;       // m (scaled)
   const double* c;       // n (scaled)
@@ -103,7 +105,8 @@ struct Ctl {
   long long k, ktot, inner_total, restarts;
   int status;       // 0 running, else PDHCG_* status
   int started;
-  int pad0, pad1;
+  int resume;       // with started = 0: re-initialise from zb / y, keep counters
+  int pad1;
   double hx[RMAX];  // R^ x of the current Halpern primal state
   double hxb[RMAX]; // R^ xbar (averaged scheme)
   unsigned long long pt[16];  // phase timers (wall-clock ticks, workgroup 0)
@@ -141,6 +144,40 @@ struct KArgs {
   double qmax;         // max_i diag(Q^)_i (first Euclidean BB step)
   int profile;         // accumulate phase timers in ctl->pt and ptimes
   unsigned long long* ptimes;   // [G][PT_COUNT] per-workgroup timers (profile)
+};
+
+// what one solver run reads besides the problem and its vectors
+struct Run {
+  const DevSettings* S;
+  const TraceBufs* T;
+  long long stop_at;             // return when ktot reaches this
+  double qmax;                   // max_i diag(Q^)_i (first Euclidean BB step)
+  unsigned long long deadline;   // wall-clock tick; 0 = none (checked at checks)
+};
+
+// one instance of a batch: its problem, vectors, trace buffers and control
+// block, solved by a single workgroup that owns every coordinate and row
+struct InstDesc {
+  DevProblem P;
+  DevVec V;
+  TraceBufs T;
+  Ctl* ctl;
+  double qmax;
+  const double* x0;   // scaled warm start (nullable), copied into zb at reset
+  const double* y0;   // scaled dual warm start (nullable)
+  int la, lr, lg;     // lanes per row of A^T / P and of A, SOC/RSOC group width
+  int n_warm;         // root warm-start slots (2 x (wave + lane items))
+};
+
+struct BatchArgs {
+  const InstDesc* desc;
+  int count;
+  const int* order;        // queue position -> instance (largest first)
+  int* queue;              // next queue position (reset to 0 before a launch)
+  DevSettings S;
+  long long stop_at;       // per-instance iteration cap of this launch
+  unsigned long long limit_ticks;   // per-launch wall-clock budget (0 = none)
+  unsigned long long* ptimes;       // [grid][PT_COUNT] phase timers, nullable
 };
 
 }  // namespace pdhcg

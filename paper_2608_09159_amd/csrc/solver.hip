@@ -32,6 +32,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "cones.hpp"
 #include "solver.hpp"
@@ -46,6 +48,7 @@ struct Lds {
   double scal[SL_COUNT];
   double hw[NWAVE][RMAX];
   double ht[RMAX];       // D^ h for the Q product of the current pass
+  double Dl[RMAX * RMAX];  // D^ (r x r), staged once per run
   double hu[RMAX];       // R^ u of the current inner iterate
   Ctl C;
   int flag;
@@ -171,14 +174,24 @@ __device__ __forceinline__ void hw_clear(Lds& L) {
 }
 
 // wave-uniform: add R[k, i] * val (0 if !active) to the wave's accumulators
-__device__ __forceinline__ void hw_add(Lds& L, const double* R, long n, int r, long i, double val,
+// (the product in the factor's precision, the sums in FP64)
+template <class MV>
+__device__ __forceinline__ void hw_add(Lds& L, const MV* R, long n, int r, long i, double val,
                                        bool active) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = 0; k < r; ++k) {
-    double t = active ? R[(size_t)k * n + i] * val : 0.0;
+    double t = active ? (double)(R[(size_t)k * n + i] * (MV)val) : 0.0;
     t = wave_sum(t);
     if (lane == 0) L.hw[wv][k] += t;
   }
+}
+
+// sum_k R[k, i] ht[k] in increasing k, accumulated in the factor's precision
+template <class MV>
+__device__ __forceinline__ double r_dot(const MV* R, long n, int r, long i, const double* ht) {
+  MV acc = 0;
+  for (int k = 0; k < r; ++k) acc += R[(size_t)k * n + i] * (MV)ht[k];
+  return (double)acc;
 }
 
 __device__ void hw_store(Lds& L, int r, double* partials, int G, int rank) {
@@ -221,26 +234,30 @@ __device__ void make_ht(Lds& L, const DevProblem& P, const double* h) {
   __syncthreads();
   if ((int)threadIdx.x < P.r) {
     double s = 0.0;
-    for (int b = 0; b < P.r; ++b) s += P.Dm[threadIdx.x * P.r + b] * h[b];
+    for (int b = 0; b < P.r; ++b) s += L.Dl[threadIdx.x * P.r + b] * h[b];
     L.ht[threadIdx.x] = s;
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ double spmv_row(const int64_t* ptr, const int* col, const double* val,
+// one CSR row times x, Lw lanes per row; products and the lane's partial
+// sum in the matrix's precision (FP32 accumulate for FP32 copies)
+template <class MV>
+__device__ __forceinline__ double spmv_row(const int64_t* ptr, const int* col, const MV* val,
                                            const double* x, long row, int sub, int Lw, bool active) {
-  double acc = 0.0;
+  MV acc = 0;
   if (active) {
     const int64_t e = ptr[row + 1];
 #pragma unroll 4
-    for (int64_t k = ptr[row] + sub; k < e; k += Lw) acc += val[k] * x[col[k]];
+    for (int64_t k = ptr[row] + sub; k < e; k += Lw) acc += val[k] * (MV)x[col[k]];
   }
-  return group_sum(acc, Lw);
+  return group_sum((double)acc, Lw);
 }
 
 // rows [r0, r1) of a CSR matrix times x into out, Lw lanes per row, this
 // workgroup only
-__device__ void spmv_range(const int64_t* ptr, const int* col, const double* val, const double* x,
+template <class MV>
+__device__ void spmv_range(const int64_t* ptr, const int* col, const MV* val, const double* x,
                            double* out, long r0, long r1, int Lw) {
   const int groups = BLOCK / Lw;
   const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
@@ -276,6 +293,21 @@ __device__ __forceinline__ void for_rows_range(long r0, long r1, int Lw, F f) {
 __device__ __forceinline__ double elem_proj(uint8_t ct, double z) {
   return ct == CT_NONNEG ? fmax(z, 0.0) : z;
 }
+
+// matrix values of the bulk sweeps (A^T y, P u, R u, A w off check
+// iterations): the FP64 data or, in FP32 mode, their FP32 copies
+template <class MV>
+struct Bulk;
+template <>
+struct Bulk<double> {
+  const double *A, *AT, *Pv, *R;
+  __device__ explicit Bulk(const DevProblem& P) : A(P.A_val), AT(P.AT_val), Pv(P.P_val), R(P.R) {}
+};
+template <>
+struct Bulk<float> {
+  const float *A, *AT, *Pv, *R;
+  __device__ explicit Bulk(const DevProblem& P) : A(P.A_valf), AT(P.AT_valf), Pv(P.P_valf), R(P.Rf) {}
+};
 
 // ---------------------------------------------------------------------------
 // metric and input views for the cone items
@@ -398,18 +430,22 @@ struct Own {
   int la, lr;   // lanes per row of A^T / P (own coordinates) and of A (own rows)
 };
 
-template <class Team>
-__device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V, Ctl* ctl,
+template <bool CONES, class MV, class Team>
+__device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, Ctl* ctl,
                            const Team& T, Lds& L, const Own& own, bool prof) {
+  const Bulk<MV> M(P);
   const int tid = threadIdx.x;
   const int rank = T.rank, G = T.size;
   const long n = P.n, m = P.m;
   const int r = P.r;
-  const DevSettings& S = A.S;
+  const DevSettings& S = *A.S;
+  const TraceBufs& TB = *A.T;
   double* part = V.partials;
   const long c0 = own.c0, c1 = own.c1, r0 = own.r0, r1 = own.r1;
   const Items& IT = own.it;
-  const bool has_items = (IT.w1 > IT.w0) || (IT.l1 > IT.l0);
+  // CONES = false: the variant for problems whose blocks are all FREE or R+,
+  // compiled without the cone projections (far fewer registers)
+  const bool has_items = CONES && ((IT.w1 > IT.w0) || (IT.l1 > IT.l0));
 
 #define SYNC_OR_EXIT()                         \
   do {                                         \
@@ -434,6 +470,9 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
     call;                                           \
     tmark(L, prof, _pc);                            \
   } while (0)
+
+  for (int e = tid; e < r * r; e += BLOCK) L.Dl[e] = P.Dm[e];
+  __syncthreads();
 
   // ------------------------------------------------------------------ init
   if (!L.C.started) {
@@ -462,14 +501,19 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
     team_reduce_h(L, part, G, r, L.C.hx);
     if (tid == 0) {
       L.C.started = 1;
-      L.C.omega = P.omega0;
-      L.C.eps_in = S.eps_in0;
+      if (!L.C.resume) {
+        L.C.omega = P.omega0;
+        L.C.eps_in = S.eps_in0;
+        L.C.ktot = 0;
+        L.C.inner_total = 0;
+        L.C.restarts = 0;
+        L.C.pid_I = 0.0;
+        L.C.e_prev = 0.0;
+      }
+      // resume (precision switch): a restart at the given point that keeps
+      // the primal weight, inner tolerance and counters
+      L.C.resume = 0;
       L.C.k = 0;
-      L.C.ktot = 0;
-      L.C.inner_total = 0;
-      L.C.restarts = 0;
-      L.C.pid_I = 0.0;
-      L.C.e_prev = 0.0;
       L.C.E0 = L.C.Eprev = L.C.lastE = 0.0;
     }
     __syncthreads();
@@ -487,7 +531,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
     const long long kt1 = L.C.ktot + 1;
     const bool check = (k == 0) || (kt1 % S.check_every == 0) || (kt1 >= S.max_iter);
     const double eps_in = L.C.eps_in;
-    const bool tracing = A.T.cap > 0 && L.C.ktot < A.T.cap;
+    const bool tracing = TB.cap > 0 && L.C.ktot < TB.cap;
     double* W = P.q_diag ? V.wx : V.u;   // the primal candidate w_x
     const MetricQ Mq = P.q_diag ? MetricQ{P.qd, 1.0, tau, 0}
                                 : (jac ? MetricQ{P.qd, 1.0 / tau, 1.0, 0} : unitM);
@@ -495,15 +539,15 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
 
     if (tracing) {
       const long kk = L.C.ktot;
-      for (long i = c0 + tid; i < c1; i += BLOCK) A.T.x[kk * n + i] = V.x[i];
-      for (long l = r0 + tid; l < r1; l += BLOCK) A.T.y[kk * m + l] = V.y[l];
+      for (long i = c0 + tid; i < c1; i += BLOCK) TB.x[kk * n + i] = V.x[i];
+      for (long l = r0 + tid; l < r1; l += BLOCK) TB.y[kk * m + l] = V.y[l];
     }
 
     // -------------------------------------------------------------- P1
     tmark(L, prof, PT_P1);
-    spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.y, V.t1, c0, c1, La);
+    spmv_range(P.AT_ptr, P.AT_col, M.AT, V.y, V.t1, c0, c1, La);
     if (!P.q_diag) {
-      if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, V.x, V.t2, c0, c1, La);
+      if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, M.Pv, V.x, V.t2, c0, c1, La);
       make_ht(L, P, L.C.hx);
     } else {
       __syncthreads();
@@ -530,8 +574,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
         if (act) {
           const double xi = V.x[i];
           const double vi = xi + tau * V.t1[i];
-          double ru = 0.0;
-          for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
+          const double ru = r_dot(M.R, n, r, i, L.ht);
           const double pu = P.P_ptr ? V.t2[i] : 0.0;
           const double g0 = pu + ru + P.c[i] + (xi - vi) / tau;
           const double z = xi - alpha0 * g0 / Mq(i);
@@ -547,7 +590,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
             V.zb[i] = z;
           }
         }
-        hw_add(L, P.R, n, r, i, un, el);
+        hw_add(L, M.R, n, r, i, un, el);
       });
       if (has_items) {
         __syncthreads();
@@ -560,7 +603,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
             const double dd = un - V.up[i];
             d2 += dd * dd;
           }
-          hw_add(L, P.R, n, r, i, un, act);
+          hw_add(L, M.R, n, r, i, un, act);
         });
       }
       const int sl[1] = {SL_DELTA2};
@@ -583,13 +626,12 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
       while (!done && jcount < jmax) {
         // ---- P3: gradient at u, BB reductions
         tmark(L, prof, PT_P3);
-        if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, V.u, V.t2, c0, c1, La);
+        if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, M.Pv, V.u, V.t2, c0, c1, La);
         make_ht(L, P, L.hu);
         double acc[3] = {0.0, 0.0, 0.0};
         for_range(c0, c1, [&](long i, bool act) {
           if (!act) return;
-          double ru = 0.0;
-          for (int kk = 0; kk < r; ++kk) ru += P.R[(size_t)kk * n + i] * L.ht[kk];
+          const double ru = r_dot(M.R, n, r, i, L.ht);
           const double ui = V.u[i];
           const double pu = P.P_ptr ? V.t2[i] : 0.0;
           const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
@@ -629,7 +671,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
             V.gp[i] = gi;
             V.u[i] = un;
           }
-          hw_add(L, P.R, n, r, i, un, el);
+          hw_add(L, M.R, n, r, i, un, el);
         });
         if (has_items) {
           PROJ(project_items(P, IT, !jac,
@@ -645,7 +687,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
               V.gp[i] = V.g[i];
               V.u[i] = un;
             }
-            hw_add(L, P.R, n, r, i, un, act);
+            hw_add(L, M.R, n, r, i, un, act);
           });
         }
         {
@@ -671,13 +713,16 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
     {
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
-        const double aw = spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, Lr, act);
+        // check iterations use the FP64 data: the residuals and the restart
+        // statistics of a check are exact FP64
+        const double aw = check ? spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, Lr, act)
+                                : spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
           const double wy = yl + sigma * (P.b[l] - (2.0 * aw - axl));
           V.wy[l] = wy;
           V.Aw[l] = aw;
-          if (tracing) A.T.wy[L.C.ktot * m + l] = wy;
+          if (tracing) TB.wy[L.C.ktot * m + l] = wy;
           if (check) {
             const double dy = yl - wy;
             acc[0] += dy * dy;                           // SL_DY2
@@ -698,7 +743,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
         double xn = 0.0;
         if (act) {
           const double xi = V.x[i], wi = W[i];
-          if (tracing) A.T.wx[L.C.ktot * n + i] = wi;
+          if (tracing) TB.wx[L.C.ktot * n + i] = wi;
           if (check) {
             const double dx = xi - wi;
             acc[5] += dx * dx;                           // SL_DX2
@@ -711,7 +756,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
             V.x[i] = xn;
           }
         }
-        if (!check) hw_add(L, P.R, n, r, i, xn, act);
+        if (!check) hw_add(L, M.R, n, r, i, xn, act);
       });
       if (check) {
         const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
@@ -740,7 +785,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
         L.C.eps_in = fmin(L.C.eps_in, fmax(S.gamma_in * sqrt(L.scal[SL_XMOV2]) / tau, S.eps_min));
         L.C.k = k + 1;
         if (tracing && rank == 0) {
-          double* sc = A.T.sc + (kt1 - 1) * 8;
+          double* sc = TB.sc + (kt1 - 1) * 8;
           sc[0] = tau; sc[1] = sigma; sc[2] = omega; sc[3] = eps_in;
           sc[4] = jcount; sc[5] = 0.0; sc[6] = 0.0; sc[7] = 0.0;
         }
@@ -771,7 +816,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
           qw = P.qd[i] * wi;
         } else {
           qw = P.P_ptr ? V.t2[i] : 0.0;
-          for (int kk = 0; kk < r; ++kk) qw += P.R[(size_t)kk * n + i] * L.ht[kk];
+          qw += r_dot(P.R, n, r, i, L.ht);
         }
         const double si = qw + P.c[i] - V.t1[i];
         acc[0] += wi * qw;                               // SL_XQX
@@ -821,6 +866,8 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
         C.status = PDHCG_NUMERICAL;
       } else if (fmax(C.rel_p, fmax(C.rel_d, C.rel_gap)) <= S.tol) {
         C.status = PDHCG_OPTIMAL;
+      } else if (A.deadline != 0ull && wall_clock64() > A.deadline) {
+        C.status = PDHCG_TIME_LIMIT;
       }
       if (C.status == 0 && rs) {
         const double dxm = sqrt(sc[SL_MOVX2]), dym = sqrt(sc[SL_MOVY2]);
@@ -835,7 +882,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
       }
       L.done = rs ? 1 : 0;
       if (tracing && rank == 0) {
-        double* t = A.T.sc + (kt1 - 1) * 8;
+        double* t = TB.sc + (kt1 - 1) * 8;
         t[0] = tau; t[1] = sigma; t[2] = omega; t[3] = eps_in;
         t[4] = jcount; t[5] = rs ? 1.0 : 0.0; t[6] = 1.0; t[7] = E;
       }
@@ -871,7 +918,7 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
             V.x[i] = xn;
           }
         }
-        if (!restart) hw_add(L, P.R, n, r, i, xn, act);
+        if (!restart) hw_add(L, M.R, n, r, i, xn, act);
       });
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
@@ -903,7 +950,8 @@ __device__ void run_solver(const KArgs& A, const DevProblem& P, const DevVec& V,
 // ---------------------------------------------------------------------------
 // single-problem kernel: the whole grid is one team
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
+template <class MV>
+__device__ void solve_body(const KArgs& A) {
   __shared__ Lds L;
   const int rank = blockIdx.x, G = gridDim.x;
   if (threadIdx.x < PT_COUNT) L.pt[threadIdx.x] = 0ull;
@@ -927,12 +975,18 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) {
   own.la = P.part_lanes[4 * rank + 0];
   own.lr = P.part_lanes[4 * rank + 1];
   GridTeam T{A.bar, A.spin_limit, rank, G};
-  run_solver(A, P, A.V, A.ctl, T, L, own, prof);
+  const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull};
+  run_solver<true, MV>(run, P, A.V, A.ctl, T, L, own, prof);
   tmark(L, prof, PT_INIT);
   __syncthreads();
   if (prof && threadIdx.x < PT_COUNT) A.ptimes[(size_t)rank * PT_COUNT + threadIdx.x] += L.pt[threadIdx.x];
   if (rank == 0 && threadIdx.x == 0 && L.C.status != PDHCG_ABORTED) *A.ctl = L.C;
 }
+
+__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<double>(A); }
+
+// FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
+__global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float>(A); }
 
 // ---------------------------------------------------------------------------
 // setup kernels: CSR SpMV and deterministic two-pass norms (power iteration)
@@ -984,15 +1038,144 @@ __global__ __launch_bounds__(BLOCK) void fill_kernel(double* x, long n, double v
 }
 
 // ---------------------------------------------------------------------------
+// batch kernels: independent instances, one workgroup per instance at a time
+// ---------------------------------------------------------------------------
+// before every batch launch: control blocks zeroed, scaled warm starts (or
+// zeros) into zb and y, root warm starts unset (NaN), queue at 0
+__global__ __launch_bounds__(BLOCK) void batch_reset_kernel(const InstDesc* desc, int count,
+                                                           int* queue) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const InstDesc& D = desc[i];
+    const long n = D.P.n, m = D.P.m;
+    for (long j = threadIdx.x; j < n; j += BLOCK) D.V.zb[j] = D.x0 ? D.x0[j] : 0.0;
+    for (long l = threadIdx.x; l < m; l += BLOCK) D.V.y[l] = D.y0 ? D.y0[l] : 0.0;
+    for (int k = threadIdx.x; k < D.n_warm; k += BLOCK) D.V.warm[k] = __builtin_nan("");
+    double* c = reinterpret_cast<double*>(D.ctl);
+    for (int k = threadIdx.x; k < (int)(sizeof(Ctl) / sizeof(double)); k += BLOCK) c[k] = 0.0;
+  }
+}
+
+// persistent batch solve: each workgroup takes the next queue position,
+// solves that instance to termination with the single-workgroup team, and
+// stores its control block; instances are queued largest first
+template <bool CONES>
+__device__ void batch_body(const BatchArgs& B) {
+  __shared__ Lds L;
+  __shared__ int slot;
+  const unsigned long long deadline = B.limit_ticks ? wall_clock64() + B.limit_ticks : 0ull;
+  const bool prof = B.ptimes != nullptr;
+  if (threadIdx.x < PT_COUNT) L.pt[threadIdx.x] = 0ull;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(B.queue, 1);
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(slot);
+    if (q >= B.count) break;
+    const int inst = __builtin_amdgcn_readfirstlane(B.order[q]);
+    const InstDesc& D = B.desc[inst];
+    if (threadIdx.x == 0) {
+      L.C = *D.ctl;
+      L.pcat = PT_INIT;
+      L.plast = wall_clock64();
+      L.epoch = 0u;
+    }
+    __syncthreads();
+    if (L.C.status == 0) {
+      Own own;
+      own.c0 = 0;
+      own.c1 = D.P.n;
+      own.r0 = 0;
+      own.r1 = D.P.m;
+      own.it = Items{0, D.P.n_wave, 0, D.P.n_lane, D.lg};
+      own.la = D.la;
+      own.lr = D.lr;
+      const Run run{&B.S, &D.T, B.stop_at, D.qmax, deadline};
+      run_solver<CONES, double>(run, D.P, D.V, D.ctl, SoloTeam{}, L, own, prof);
+      tmark(L, prof, PT_INIT);
+      __syncthreads();
+      if (threadIdx.x == 0) *D.ctl = L.C;
+    }
+    __syncthreads();
+  }
+  if (prof && threadIdx.x < PT_COUNT) B.ptimes[(size_t)blockIdx.x * PT_COUNT + threadIdx.x] = L.pt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs B) { batch_body<true>(B); }
+
+// batches without cone blocks: 4 waves per SIMD (two instances per CU)
+__global__ __launch_bounds__(BLOCK, 4) void batch_kernel_lin(BatchArgs B) { batch_body<false>(B); }
+
+// ||A^||_2 of every instance: the power iteration of the single-problem
+// setup (128 steps of A^T A from 1/sqrt(n), normalised each step), one
+// workgroup per instance; out[i] = sqrt of the last norm (0 if A is empty)
+__global__ __launch_bounds__(BLOCK) void batch_power_kernel(const InstDesc* desc, int count, int iters,
+                                                           double* out) {
+  __shared__ double red[NWAVE];
+  __shared__ double nrm;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const DevProblem& P = desc[i].P;
+    const DevVec& V = desc[i].V;
+    const long n = P.n, m = P.m;
+    double* z = V.v;
+    double* t = V.Aw;
+    double* w = V.g;
+    if (m == 0 || P.A_ptr[m] == 0) {
+      if (threadIdx.x == 0) out[i] = 0.0;
+      continue;
+    }
+    const double z0 = 1.0 / sqrt((double)n);
+    for (long j = threadIdx.x; j < n; j += BLOCK) z[j] = z0;
+    __syncthreads();
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+      spmv_range(P.A_ptr, P.A_col, P.A_val, z, t, 0, m, desc[i].lr);
+      __syncthreads();
+      spmv_range(P.AT_ptr, P.AT_col, P.AT_val, t, w, 0, n, desc[i].la);
+      __syncthreads();
+      double s = 0.0;
+      for (long j = threadIdx.x; j < n; j += BLOCK) s += w[j] * w[j];
+      s = wave_sum(s);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < NWAVE; ++k) tot += red[k];
+        nrm = sqrt(tot);
+      }
+      __syncthreads();
+      const double f = nrm;
+      for (long j = threadIdx.x; j < n; j += BLOCK) z[j] = f > 0.0 ? w[j] / f : w[j];
+      lam = f;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sqrt(lam);
+    __syncthreads();
+  }
+}
+
+// pack every instance's candidate (w_x, w_y) into contiguous outputs
+__global__ __launch_bounds__(BLOCK) void batch_gather_kernel(const InstDesc* desc, int count,
+                                                            const long* offx, const long* offy,
+                                                            double* ox, double* oy) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const InstDesc& D = desc[i];
+    const double* W = D.P.q_diag ? D.V.wx : D.V.u;
+    const long n = D.P.n, m = D.P.m;
+    for (long j = threadIdx.x; j < n; j += BLOCK) ox[offx[i] + j] = W[j];
+    for (long l = threadIdx.x; l < m; l += BLOCK) oy[offy[i] + l] = D.V.wy[l];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
 int block_size() { return BLOCK; }
 
-hipError_t launch_solve(const KArgs& args, int grid, hipStream_t stream) {
+hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream) {
   KArgs a = args;
   void* params[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)solve_kernel, dim3(grid), dim3(BLOCK), params, 0,
-                                    stream);
+  const void* k = fp32 ? (const void*)solve_kernel_f32 : (const void*)solve_kernel;
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BLOCK), params, 0, stream);
 }
 
 hipError_t max_coop_grid(int* out) {
@@ -1003,7 +1186,10 @@ hipError_t max_coop_grid(int* out) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)solve_kernel, BLOCK, 0);
   if (e != hipSuccess) return e;
-  *out = per * ncu;
+  int per32 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)solve_kernel_f32, BLOCK, 0);
+  if (e != hipSuccess) return e;
+  *out = std::min(per, per32) * ncu;
   return hipSuccess;
 }
 
@@ -1041,6 +1227,41 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t st) {
   int grid = (int)((n + BLOCK - 1) / BLOCK);
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(BLOCK), 0, st, x, n, v);
+  return hipGetLastError();
+}
+
+int batch_grid_limit(bool cones) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+  const void* k = cones ? (const void*)batch_kernel : (const void*)batch_kernel_lin;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, BLOCK, 0) != hipSuccess) return ncu;
+  return std::max(1, per * ncu);
+}
+
+hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t st) {
+  if (cones) hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(BLOCK), 0, st, args);
+  else hipLaunchKernelGGL(batch_kernel_lin, dim3(grid), dim3(BLOCK), 0, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipStream_t st) {
+  const int grid = std::max(1, std::min(count, 4096));
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(grid), dim3(BLOCK), 0, st, desc, count, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double* out, hipStream_t st) {
+  const int grid = std::max(1, std::min(count, batch_grid_limit(false)));
+  hipLaunchKernelGGL(batch_power_kernel, dim3(grid), dim3(BLOCK), 0, st, desc, count, iters, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx, const long* offy,
+                               double* ox, double* oy, hipStream_t st) {
+  const int grid = std::max(1, std::min(count, 4096));
+  hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(BLOCK), 0, st, desc, count, offx, offy, ox,
+                     oy);
   return hipGetLastError();
 }
 

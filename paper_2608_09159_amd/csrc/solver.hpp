@@ -7,12 +7,20 @@
 namespace pdhcg {
 
 int block_size();
-hipError_t launch_solve(const KArgs& args, int grid, hipStream_t stream);
+hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream);
 hipError_t max_coop_grid(int* out);
 hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, const double* x,
                        double* y, long rows, int Lw, hipStream_t st);
 hipError_t launch_norm(const double* x, long n, double* part, double* nrm, hipStream_t st);
 hipError_t launch_scale(double* x, long n, const double* nrm, hipStream_t st);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t st);
+
+// batch solve (one workgroup per instance)
+int batch_grid_limit(bool cones);
+hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t st);
+hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipStream_t st);
+hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double* out, hipStream_t st);
+hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx, const long* offy,
+                               double* ox, double* oy, hipStream_t st);
 
 }  // namespace pdhcg

@@ -1,0 +1,113 @@
+"""Shared parity helpers of the GPU tests: library results against the CPU
+oracle (iterate traces, final residuals, KKT rechecks) and a problem whose
+cone blocks stress the work mapping."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2608_09159_amd as G
+from instances import Problem, synth
+from oracle import pdhg
+
+ITER_TOL = 1e-10
+FINAL_TOL = 1e-6
+
+
+def _rel(a, b):
+    scale = max(float(np.max(np.abs(b))) if b.size else 0.0, 1e-300)
+    return float(np.max(np.abs(a - b))) / scale if b.size else 0.0
+
+
+def oracle_settings(**kw):
+    st = pdhg.Settings()
+    for k, v in kw.items():
+        setattr(st, k, v)
+    return st
+
+
+def trace_parity(prob, iters=50, check_every=4, x0=None, y0=None, **kw):
+    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a")}
+    print(f"[parity] {prob.name} n={prob.n} m={prob.m} iters={iters} {kw}", flush=True)
+    h = G.setup(prob, trace_iters=iters, check_every=check_every, max_iter=iters, **kw)
+    try:
+        g = h.solve(x0, y0)
+        tr = h.trace(iters)
+    finally:
+        h.free()
+    o = pdhg.solve(prob, oracle_settings(trace_iters=iters, check_every=check_every,
+                                         max_iter=iters, **okw), x0=x0, y0=y0)
+    assert_trace_matches(prob.name, tr, o)
+    return g, o
+
+
+def assert_trace_matches(name, tr, o):
+    """Library trace `tr` against the oracle result `o`, iteration by
+    iteration (the inner-step counts, check and restart decisions exactly)."""
+    prob_name = name
+    assert tr["count"] == len(o.trace), (tr["count"], len(o.trace))
+    last = tr["count"] - 1
+    for k, ot in enumerate(o.trace):
+        for key in ("x", "y", "wx", "wy"):
+            err = _rel(tr[key][k], ot[key])
+            assert err <= ITER_TOL, (prob_name, k, key, err)
+        for key in ("tau", "sigma", "omega", "eps_in"):
+            assert tr[key][k] == pytest.approx(ot[key], rel=ITER_TOL), (prob_name, k, key)
+        assert tr["inner"][k] == ot["inner"], (prob_name, k, "inner")
+        if k < last or o.status == "OPTIMAL":
+            assert bool(tr["check"][k]) == bool(ot["check"]), (prob_name, k, "check")
+            assert bool(tr["restart"][k]) == bool(ot["restart"]), (prob_name, k, "restart")
+            if ot["check"]:
+                assert tr["E"][k] == pytest.approx(ot["E"], rel=1e-9, abs=1e-300)
+
+
+def final_parity(prob, **kw):
+    print(f"[final] {prob.name} n={prob.n} m={prob.m} {kw}", flush=True)
+    g = G.solve(prob, **kw)
+    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a")}
+    o = pdhg.solve(prob, oracle_settings(**okw))
+    assert_final_matches(g, o)
+    return g, o
+
+
+def assert_final_matches(g, o):
+    """Status, the three relative KKT residuals (absolute difference) and the
+    objectives (relative difference) of a library result against the oracle."""
+    assert g["status"] == o.status
+    for key in ("rel_primal", "rel_dual", "rel_gap"):
+        assert abs(g[key] - o.kkt[key]) <= FINAL_TOL, (key, g[key], o.kkt[key])
+    for key in ("primal_obj", "dual_obj"):
+        assert abs(g[key] - o.kkt[key]) <= FINAL_TOL * max(1.0, abs(o.kkt[key])), key
+
+
+def recheck_kkt(prob, g, tol):
+    """Residuals of the returned point recomputed on the CPU agree with the
+    library's own and meet the tolerance."""
+    k = pdhg.kkt_residuals(prob, g["x"], g["y"])
+    for key in ("rel_primal", "rel_dual", "rel_gap"):
+        assert k[key] <= tol * 1.001, (key, k[key])
+        assert abs(k[key] - g[key]) <= 1e-8, (key, k[key], g[key])
+
+
+def edge_cone_problem(seed=0, m=9):
+    """Blocks that stress the work mapping: an SOC longer than one wavefront,
+    an RSOC without v part, a 1-dimensional SOC, power cones with extreme
+    exponents, free coordinates."""
+    rng = np.random.default_rng(seed)
+    spec = [("soc", 150, 0.0), ("rsoc", 2, 0.0), ("soc", 1, 0.0), ("pow", 3, 0.05),
+            ("pow", 3, 0.95), ("exp", 3, 0.0), ("rsoc", 70, 0.0), ("free", 3, 0.0),
+            ("nonneg", 5, 0.0)]
+    cones, st = [], 0
+    for kind, d, al in spec:
+        cones.append((kind, st, d, al))
+        st += d
+    n = st
+    A = sp.random(m, n, density=0.3, random_state=rng, data_rvs=rng.standard_normal, format="csr")
+    x0 = synth._interior_point(rng, n, cones)
+    P = sp.diags(rng.uniform(0.1, 1.0, size=n)).tocsr()
+    R = rng.standard_normal((3, n)) / math.sqrt(n)
+    return Problem(n=n, m=m, A=A, b=A @ x0, c=rng.standard_normal(n), P=P, R=R, D=np.eye(3),
+                   cones=cones, name="edge_cones")
+
+

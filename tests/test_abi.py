@@ -106,3 +106,26 @@ def test_rejects_bad_settings(lib):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError):
         G.load(str(tmp_path / "nope.so"))
+
+
+def test_batch_rejects_invalid_member(lib):
+    """A batch is validated instance by instance on the host before any
+    device work; one bad member fails the whole setup."""
+    good = synth.portfolio(1_000_000, n_assets=60)
+    p = synth.tiny_nonneg_qp(0)
+    bad = Problem(n=p.n, m=p.m, A=p.A, b=p.b, c=p.c, P=p.P, cones=[("nonneg", 0, p.n - 1, 0.0)])
+    ms = [G._Marshalled(q) for q in (good, bad, good)]
+    arr = (G.ProblemC * 3)(*[m.pc for m in ms])
+    h = C.c_void_p()
+    rc = G.load().pdhcg_setup(arr, 3, C.byref(G.default_settings()), C.byref(h))
+    assert rc == -4 and h.value is None
+
+
+def test_batch_binding_needs_two_problems(lib):
+    with pytest.raises(ValueError):
+        G.setup_batch([synth.tiny_qp(0)])
+
+
+def test_defaults_of_execution_settings(lib):
+    s = G.default_settings()
+    assert s.autotune == 1 and s.tune_iters == 64 and s.time_kernels == 0
