@@ -185,7 +185,32 @@ def bench_batch(args, probs, wname):
                      "kernel": "batch_kernel (graph: reset + batch + gather)",
                      "kernel_avg_launch_ms": 1e3 * kmed, "launch": [last[0]["grid_dim"], last[0]["block_dim"]]},
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def fp32_variant(prob, args, t64, g64):
+    """The same solve in FP32-bulk mode with the FP64 polish, timed like the
+    FP64 solve; error of its result against the FP64 GPU result."""
+    import torch
+    import paper_2608_09159_amd as pkg
+    stream = torch.cuda.current_stream()
+    h = pkg.setup(prob, tol=args.tol, precision="fp32", time_kernels=1, stream=stream.cuda_stream)
+    for _ in range(args.warmup):
+        h.solve()
+    torch.cuda.synchronize()
+    walls, r = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        r = h.solve()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    h.free()
+    t32 = float(np.median(walls))
+    return {"time_to_tol_s": t32, "speedup_vs_fp64": t64 / t32, "status": r["status"],
+            "iterations": r["iterations"], "polish_iterations": r["polish_iterations"],
+            "rel_kkt": max(r["rel_primal"], r["rel_dual"], r["rel_gap"]),
+            "x_rel_err_vs_fp64": float(np.linalg.norm(r["x"] - g64["x"]) / np.linalg.norm(g64["x"])),
+            "obj_rel_diff_vs_fp64": abs(r["primal_obj"] - g64["primal_obj"]) / max(1.0, abs(g64["primal_obj"]))}
 
 
 def main():
@@ -196,6 +221,8 @@ def main():
     ap.add_argument("--workload", default="mixed_cone")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32-bulk and batched comparisons of the default line")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--loop-sample", type=int, default=4096,
                     help="portfolio_batch: instances timed in the per-instance loop baseline")
@@ -215,7 +242,7 @@ def main():
         build.build()
     prob, wname = workload(args.workload)
     if args.workload == "portfolio_batch":
-        bench_batch(args, prob, wname)
+        print(json.dumps(bench_batch(args, prob, wname)), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
@@ -277,6 +304,18 @@ def main():
                      "launch": [grid, runs[-1]["block_dim"]],
                      "algorithmic_bytes_per_iteration": alg_bytes / iters},
     }
+    if not args.no_variants and args.workload == "mixed_cone":
+        wall1 = wall / args.steps
+        out["variants"] = {"fp32_bulk": fp32_variant(prob, args, wall1, last)}
+        bargs = argparse.Namespace(**{**vars(args), "loop_sample": 128})
+        bw, bname = workload("portfolio_batch")
+        bo = bench_batch(bargs, bw, bname)
+        out["variants"]["batched"] = {
+            "workload": bname, "time_to_tol_s": bo["time_to_tol_s"],
+            "loop_time_to_tol_s": bo["loop_baseline"]["time_to_tol_s"],
+            "loop_instances_timed": bo["loop_baseline"]["instances_timed"],
+            "speedup_vs_loop": bo["speedup_vs_loop"], "statuses": bo["statuses"],
+            "iters_per_s": bo["value"], "roofline_frac": bo["roofline"]["frac"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
     print(json.dumps(out), flush=True)

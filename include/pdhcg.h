@@ -240,6 +240,13 @@ int pdhcg_get_trace(void* h, int32_t inst, pdhcg_trace* t);
 int pdhcg_get_scaling(void* h, int32_t inst, double* Sx, double* Sy,
                       double* nu_b, double* nu_c, double* eta, double* omega0);
 
+/* Diagnostics of a PDHCG_NUMERICAL status on the current device: *count =
+ * number of cone projections of the last solve (or batch) whose
+ * root-finding failed; rec[0..7] = the first one's (cone type, r[0..2],
+ * metric m[0..2], alpha), zeros when *count is 0.  Reads device memory; call
+ * after the solve has returned.                                            */
+int pdhcg_last_cone_failure(double* rec, int64_t* count);
+
 /* Release every host and device resource of h (NULL is a no-op).          */
 void pdhcg_free(void* h);
 
@@ -248,6 +255,49 @@ const char* pdhcg_strerror(int code);
 
 /* Library version string.                                                  */
 const char* pdhcg_version(void);
+
+/* ---- learned warm start ------------------------------------------------
+ * A ReLU multilayer perceptron, dims[0] -> dims[1] -> ... -> dims[layers],
+ * trained on (instance parameters -> primal-dual solution) pairs produced by
+ * the solver itself; its prediction seeds pdhcg_solve, which still runs to
+ * the same tolerance.  The paper has no learned component: the network is
+ * this library's own (Z_l = H_{l-1} W_l + b_l, H_l = relu(Z_l) below the
+ * output layer, mean-squared-error loss, Adam).  Matrix products run on the
+ * matrix cores with BF16 operands (input, weights, activations and backward
+ * signals rounded to nearest-even BF16) and FP32 accumulation; master
+ * weights, biases, gradients and Adam moments are FP32.
+ *
+ * Pointers named x, y in forward/train_step are DEVICE pointers (row-major
+ * batch x dims[0] inputs, batch x dims[layers] targets/outputs, FP32), e.g.
+ * the data of torch CUDA tensors; parameters and gradients are exchanged
+ * through HOST pointers.  W of layer l is dims[l] x dims[l+1] row-major.
+ * All work is issued on `stream`.  Handles are not thread-safe.            */
+typedef struct {
+    double lr, beta1, beta2, eps;       /* e.g. 1e-3, 0.9, 0.999, 1e-8      */
+} pdhcg_adam;
+
+/* Allocate a network (weights zero) for batches of up to max_batch rows.
+ * Errors: PDHCG_E_ARG (null/invalid sizes), PDHCG_E_SHAPE (a dim < 1),
+ * PDHCG_E_MEM, PDHCG_E_HIP.                                               */
+int pdhcg_mlp_create(int32_t layers, const int32_t* dims, int32_t max_batch,
+                     void* stream, void** out);
+/* Set the FP32 weights (host, dims[l] x dims[l+1]) and bias (host, dims[l+1])
+ * of layer l; resets that layer's Adam moments and the step count.         */
+int pdhcg_mlp_set_params(void* h, int32_t layer, const float* W, const float* b);
+/* Copy layer l's FP32 weights / bias to host buffers (each nullable).      */
+int pdhcg_mlp_get_params(void* h, int32_t layer, float* W, float* b);
+/* y (device, batch x dims[layers]) = network(x) (device, batch x dims[0]).  */
+int pdhcg_mlp_forward(void* h, const float* x, int32_t batch, float* y);
+/* One step on the batch (x, y): forward, loss, backward, and an Adam update
+ * when opt is non-NULL (opt = NULL computes the gradients only; read them
+ * with pdhcg_mlp_get_grads).  *loss (host, nullable) receives the mean
+ * squared error of the forward pass before the update.                     */
+int pdhcg_mlp_train_step(void* h, const float* x, const float* y, int32_t batch,
+                         const pdhcg_adam* opt, double* loss);
+/* Copy layer l's gradients of the last train step (host, nullable).        */
+int pdhcg_mlp_get_grads(void* h, int32_t layer, float* dW, float* db);
+/* Release the network (NULL is a no-op).                                   */
+void pdhcg_mlp_free(void* h);
 
 #ifdef __cplusplus
 }

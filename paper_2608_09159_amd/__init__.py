@@ -91,7 +91,13 @@ _LIB = None
 
 EXPORTS = ("pdhcg_default_settings", "pdhcg_setup", "pdhcg_solve", "pdhcg_solve_batch",
            "pdhcg_get_trace", "pdhcg_get_scaling", "pdhcg_free", "pdhcg_strerror",
-           "pdhcg_version")
+           "pdhcg_version", "pdhcg_last_cone_failure", "pdhcg_mlp_create", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
+           "pdhcg_mlp_forward", "pdhcg_mlp_train_step", "pdhcg_mlp_get_grads", "pdhcg_mlp_free")
+
+
+class AdamC(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
 
 
 def lib_path():
@@ -121,6 +127,17 @@ def load(path=None):
     lib.pdhcg_strerror.argtypes = [C.c_int]
     lib.pdhcg_strerror.restype = C.c_char_p
     lib.pdhcg_version.restype = C.c_char_p
+    lib.pdhcg_last_cone_failure.argtypes = [_dp, C.POINTER(C.c_int64)]
+    _fp = C.POINTER(C.c_float)
+    lib.pdhcg_mlp_create.argtypes = [C.c_int32, _i32p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.pdhcg_mlp_set_params.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
+    lib.pdhcg_mlp_get_params.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
+    lib.pdhcg_mlp_get_grads.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
+    lib.pdhcg_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.pdhcg_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.POINTER(AdamC), C.POINTER(C.c_double)]
+    lib.pdhcg_mlp_free.argtypes = [C.c_void_p]
+    lib.pdhcg_mlp_free.restype = None
     if path is None:
         _LIB = lib
     return lib
@@ -275,6 +292,16 @@ def _result_dict(res, x, y, s):
     return out
 
 
+def last_cone_failure():
+    """(count, record) of failed cone root-finding in the last solve:
+    record = (cone type, r0, r1, r2, m0, m1, m2, alpha)."""
+    rec = np.zeros(8)
+    cnt = C.c_int64()
+    _check(load().pdhcg_last_cone_failure(_ptr(rec, C.c_double), C.byref(cnt)),
+           "pdhcg_last_cone_failure")
+    return int(cnt.value), rec
+
+
 class BatchHandle(Handle):
     """Handle of a batch (pdhcg_setup with count > 1)."""
 
@@ -348,3 +375,80 @@ def solve(prob, x0=None, y0=None, want_s=False, **kw):
         return h.solve(x0, y0, want_s=want_s)
     finally:
         h.free()
+
+
+class MLP:
+    """The warm-start network (pdhcg_mlp_*): ReLU MLP with BF16 matrix
+    operands, FP32 master weights and Adam.  Inputs and targets are torch
+    CUDA float32 tensors (device pointers); parameters are numpy arrays."""
+
+    def __init__(self, dims, max_batch, stream=None):
+        lib = load()
+        self.dims = [int(d) for d in dims]
+        self.layers = len(self.dims) - 1
+        self.max_batch = int(max_batch)
+        arr = np.ascontiguousarray(self.dims, dtype=np.int32)
+        h = C.c_void_p()
+        st = getattr(stream, "cuda_stream", stream)
+        _check(lib.pdhcg_mlp_create(self.layers, _ptr(arr, C.c_int32), self.max_batch, st,
+                                    C.byref(h)), "pdhcg_mlp_create")
+        self.ptr = h.value
+
+    def set_params(self, layer, W, b):
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        assert W.shape == (self.dims[layer], self.dims[layer + 1]) and b.shape == (self.dims[layer + 1],)
+        _check(load().pdhcg_mlp_set_params(self.ptr, layer, _ptr(W, C.c_float), _ptr(b, C.c_float)),
+               "pdhcg_mlp_set_params")
+
+    def get_params(self, layer):
+        W = np.zeros((self.dims[layer], self.dims[layer + 1]), dtype=np.float32)
+        b = np.zeros(self.dims[layer + 1], dtype=np.float32)
+        _check(load().pdhcg_mlp_get_params(self.ptr, layer, _ptr(W, C.c_float), _ptr(b, C.c_float)),
+               "pdhcg_mlp_get_params")
+        return W, b
+
+    def grads(self, layer):
+        dW = np.zeros((self.dims[layer], self.dims[layer + 1]), dtype=np.float32)
+        db = np.zeros(self.dims[layer + 1], dtype=np.float32)
+        _check(load().pdhcg_mlp_get_grads(self.ptr, layer, _ptr(dW, C.c_float), _ptr(db, C.c_float)),
+               "pdhcg_mlp_get_grads")
+        return dW, db
+
+    @staticmethod
+    def _dev(t, cols):
+        if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4
+                and t.is_contiguous() and t.dim() == 2 and t.shape[1] == cols):
+            raise ValueError("expected a contiguous CUDA float32 tensor with %d columns" % cols)
+        return t.data_ptr()
+
+    def forward(self, x, out=None):
+        import torch
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty((B, self.dims[-1]), dtype=torch.float32, device=x.device)
+        _check(load().pdhcg_mlp_forward(self.ptr, self._dev(x, self.dims[0]), B,
+                                        self._dev(out, self.dims[-1])), "pdhcg_mlp_forward")
+        return out
+
+    def train_step(self, x, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, update=True):
+        """One step on (x, y); returns the batch loss before the update."""
+        B = int(x.shape[0])
+        opt = AdamC(lr, beta1, beta2, eps) if update else None
+        loss = C.c_double()
+        _check(load().pdhcg_mlp_train_step(self.ptr, self._dev(x, self.dims[0]),
+                                           self._dev(y, self.dims[-1]), B,
+                                           C.byref(opt) if opt is not None else None,
+                                           C.byref(loss)), "pdhcg_mlp_train_step")
+        return loss.value
+
+    def free(self):
+        if self.ptr:
+            load().pdhcg_mlp_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpdhcg.so")
-SOURCES = ["api.cpp", "host_setup.cpp", "solver.hip"]
+SOURCES = ["api.cpp", "host_setup.cpp", "solver.hip", "mlp.hip", "mlp_api.cpp"]
 ARCH = os.environ.get("PDHCG_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,7 +28,7 @@ def flags():
             "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False, jobs=3):
+def build(verbose=False, jobs=5):
     cc = hipcc()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)

@@ -942,6 +942,7 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   }
   Ctl c0;
   std::memset(&c0, 0, sizeof(c0));
+  HIPCHK(reset_cone_failure(st));
   HIPCHK(hipMemcpyAsync(I->ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(I->bar, 0, I->bar_bytes, st));
   HIPCHK(launch_fill(I->V.warm, I->n_warm, NAN, st));
@@ -1081,6 +1082,7 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
   }
   int rc = capture_batch(h);
   if (rc != PDHCG_OK) return rc;
+  HIPCHK(reset_cone_failure(st));
   const bool timing = h->s.time_kernels != 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (timing) {
@@ -1145,6 +1147,16 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
   return PDHCG_OK;
 }
 
+
+int pdhcg_last_cone_failure(double* rec, int64_t* count) {
+  if (!rec || !count) return PDHCG_E_ARG;
+  unsigned cnt = 0;
+  if (read_cone_failure(rec, &cnt) != hipSuccess) return PDHCG_E_HIP;
+  *count = cnt;
+  if (cnt == 0)
+    for (int i = 0; i < 8; ++i) rec[i] = 0.0;
+  return PDHCG_OK;
+}
 
 int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {
   Handle* h = (Handle*)hv;

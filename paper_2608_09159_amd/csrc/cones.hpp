@@ -553,6 +553,26 @@ __device__ bool exp_newton(const ExpData& e, double rho, double out[3], double* 
   return false;
 }
 
+// diagnostics: the inputs of the first cone projection of a solve whose
+// root-finding failed, and the number of failures (read by the host with
+// pdhcg_last_cone_failure; reset before every solve)
+__device__ double g_cone_fail[8];
+__device__ unsigned int g_cone_fail_count;
+
+__device__ void note_cone_failure(int type, double a, double b, double c, double ma, double mb, double mc,
+                                  double al) {
+  if (atomicAdd(&g_cone_fail_count, 1u) == 0u) {
+    g_cone_fail[0] = (double)type;
+    g_cone_fail[1] = a;
+    g_cone_fail[2] = b;
+    g_cone_fail[3] = c;
+    g_cone_fail[4] = ma;
+    g_cone_fail[5] = mb;
+    g_cone_fail[6] = mc;
+    g_cone_fail[7] = al;
+  }
+}
+
 __device__ __noinline__ void project_exp(double r0, double s0, double t0, double mr, double ms, double mt,
                             double out[3], double* warm) {
   if (exp_in_cone(r0, s0, t0)) { out[0] = r0; out[1] = s0; out[2] = t0; return; }
@@ -605,6 +625,20 @@ __device__ __noinline__ void project_exp(double r0, double s0, double t0, double
     exp_point(e, fallback, out);
     if (out[1] >= 0.0) return;
   }
+  {
+    // no admissible root survives in floating point: when -M r lies within
+    // rounding of the boundary of K^* (the dual slack of a solved block sits
+    // there), the projection is 0 to rounding, since |Pi(r)| = dist(r, -K^*)
+    const double a = -mr * r0, b = -ms * s0, c = -mt * t0;
+    if (a < 0.0) {
+      const double lhs = -a * exp(b / a), rhs = 2.718281828459045 * c;
+      if (lhs - rhs <= 1e-12 * (fabs(lhs) + fabs(rhs))) {
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+      }
+    }
+  }
+  note_cone_failure(PDHCG_CONE_EXP, r0, s0, t0, mr, ms, mt, 0.0);
   out[0] = out[1] = out[2] = NAN;   // reported as a numerical failure
 }
 

@@ -1,0 +1,266 @@
+// Kernels of the warm-start network: a ReLU MLP trained and evaluated with
+// BF16 matrix operands on the gfx950 matrix cores (FP32 accumulation), FP32
+// master weights and Adam.
+//
+// GEMM: C[M x N] = op(A)[M x K] * op(B)[K x N], all matrices row-major.
+//   A: M x K (TA = false) or stored K x M (TA = true, used transposed)
+//   B: K x N (TB = false) or stored N x K (TB = true, used transposed)
+// Workgroup tile 64 x 64 x 32, four waves, each wave one 32 x 32 output
+// block computed with v_mfma_f32_32x32x16_bf16 (two per K step).  Both
+// operand tiles are staged in LDS with K contiguous (row stride padded by 8
+// elements), so every lane reads its 8-element fragment with one 16-byte LDS
+// load.  Long K is split over `splits` workgroups writing FP32 partial tiles;
+// a second kernel sums them in a fixed order and applies the epilogue, so
+// results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "mlp.hpp"
+
+namespace pdhcg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
+constexpr int GT = 256;   // threads per GEMM workgroup
+
+struct GemmArgs {
+  const __bf16* A;
+  const __bf16* B;
+  long lda, ldb;
+  int M, N, K;
+  int kchunk;             // K range of one split (multiple of TK)
+  int epi;
+  const float* bias;      // EPI_BIAS_*
+  const __bf16* mask;     // EPI_MASK_BF16: M x N, ld = N
+  float* outf;            // FP32 output (ld = N) or partials [splits][M][N]
+  __bf16* outb;           // BF16 output (ld = N)
+  int partial;            // 1: write FP32 partials of split blockIdx.z
+};
+
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float acc) {
+  const size_t o = (size_t)m * g.N + n;
+  switch (g.epi) {
+    case EPI_F32: g.outf[o] = acc; break;
+    case EPI_BIAS_F32: g.outf[o] = acc + g.bias[n]; break;
+    case EPI_BIAS_RELU_BF16: g.outb[o] = (__bf16)fmaxf(acc + g.bias[n], 0.0f); break;
+    case EPI_MASK_BF16: g.outb[o] = (__bf16)((float)g.mask[o] > 0.0f ? acc : 0.0f); break;
+    default: break;
+  }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(GT) void gemm_kernel(GemmArgs g) {
+  __shared__ __bf16 As[TM][LDK];
+  __shared__ __bf16 Bs[TN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = blockIdx.z * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  f32x16 acc = {};
+  const __bf16 zero = (__bf16)0.0f;
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+    // ---- stage A tile (TM x TK) as As[m][k]
+    if (!TA) {
+      const int r = tid >> 2, kq = (tid & 3) * 8;
+      const int m = m0 + r;
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kq + j;
+        As[r][kq + j] = (m < g.M && k < ke) ? g.A[(size_t)m * g.lda + k] : zero;
+      }
+    } else {
+      const int kk = tid >> 3, mq = (tid & 7) * 8;
+      const int k = k0 + kk;
+      for (int j = 0; j < 8; ++j) {
+        const int m = m0 + mq + j;
+        As[mq + j][kk] = (m < g.M && k < ke) ? g.A[(size_t)k * g.lda + m] : zero;
+      }
+    }
+    // ---- stage B tile (TK x TN) as Bs[n][k]
+    if (!TB) {
+      const int kk = tid >> 3, nq = (tid & 7) * 8;
+      const int k = k0 + kk;
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + nq + j;
+        Bs[nq + j][kk] = (n < g.N && k < ke) ? g.B[(size_t)k * g.ldb + n] : zero;
+      }
+    } else {
+      const int r = tid >> 2, kq = (tid & 3) * 8;
+      const int n = n0 + r;
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kq + j;
+        Bs[r][kq + j] = (n < g.N && k < ke) ? g.B[(size_t)n * g.ldb + k] : zero;
+      }
+    }
+    __syncthreads();
+    // ---- two 32x32x16 steps; lane l holds row/col (l % 32), k (l / 32) * 8 + j
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + (lane & 31)][ks + (lane >> 5) * 8]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + (lane & 31)][ks + (lane >> 5) * 8]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // ---- output: acc[j] is row (j / 4) * 8 + (l / 32) * 4 + j % 4, column l % 32
+  const int n = n0 + wn + (lane & 31);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int m = m0 + wm + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
+    if (m < g.M && n < g.N) {
+      if (g.partial) g.outf[((size_t)blockIdx.z * g.M + m) * g.N + n] = acc[j];
+      else epilogue(g, m, n, acc[j]);
+    }
+  }
+}
+
+// sum the split-K partials in split order, then the epilogue
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, const float* part, int splits) {
+  const long total = (long)g.M * g.N;
+  for (long o = (long)blockIdx.x * 256 + threadIdx.x; o < total; o += (long)gridDim.x * 256) {
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * total + o];
+    epilogue(g, (int)(o / g.N), (int)(o % g.N), s);
+  }
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* x, __bf16* y, long n) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) y[i] = (__bf16)x[i];
+}
+
+// dZ = bf16(scale * (yhat - y)); per-block partial of sum (yhat - y)^2 in FP64
+__global__ __launch_bounds__(256) void mse_grad_kernel(const float* yhat, const float* y, __bf16* dz, long n,
+                                                      float scale, double* part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const float d = yhat[i] - y[i];
+    dz[i] = (__bf16)(scale * d);
+    s += (double)d * (double)d;
+  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(64) void sum_partials_kernel(const double* part, int np, double* out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += part[i];
+    out[0] = s;
+  }
+}
+
+// db[n] = sum over rows of dz[b][n] (FP32, rows in order)
+__global__ __launch_bounds__(256) void colsum_kernel(const __bf16* dz, int rows, int N, float* db) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int b = 0; b < rows; ++b) s += (float)dz[(size_t)b * N + n];
+  db[n] = s;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* w, __bf16* wb, const float* g, float* m, float* v,
+                                                  long n, AdamStep a) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = a.b1 * m[i] + a.omb1 * gi;
+    const float vi = a.b2 * v[i] + a.omb2 * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    w[i] = wi;
+    if (wb) wb[i] = (__bf16)wi;
+  }
+}
+
+int grid_for(long n, int per, int cap) {
+  long g = (n + per - 1) / per;
+  return (int)std::max<long>(1, std::min<long>(g, cap));
+}
+
+}  // namespace
+
+hipError_t mlp_gemm(const __bf16* A, bool ta, long lda, const __bf16* B, bool tb, long ldb, int M, int N,
+                    int K, int epi, const float* bias, const __bf16* mask, float* outf, __bf16* outb,
+                    float* work, size_t work_floats, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.epi = epi;
+  g.bias = bias;
+  g.mask = mask;
+  g.outf = outf;
+  g.outb = outb;
+  const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  // split K until there are about 1024 workgroups (and the partials fit)
+  const int ksteps = std::max(1, (K + TK - 1) / TK);
+  int splits = 1;
+  while (tiles * splits < 1024 && splits * 2 <= ksteps &&
+         (size_t)(splits * 2) * (size_t)M * (size_t)N <= work_floats)
+    splits *= 2;
+  const int per = (ksteps + splits - 1) / splits;
+  g.kchunk = per * TK;
+  splits = (ksteps + per - 1) / per;
+  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, splits);
+  if (splits > 1) {
+    g.partial = 1;
+    GemmArgs p = g;
+    p.outf = work;
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(GT), 0, st, p);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(GT), 0, st, p);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(GT), 0, st, p);
+    else hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(GT), 0, st, p);
+    g.partial = 0;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((long)M * N, 256, 4096)), dim3(256), 0, st, g,
+                       work, splits);
+  } else {
+    g.partial = 0;
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(GT), 0, st, g);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(GT), 0, st, g);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(GT), 0, st, g);
+    else hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(GT), 0, st, g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(const float* x, __bf16* y, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_mse_grad(const float* yhat, const float* y, __bf16* dz, long n, float scale, double* part,
+                        double* loss, hipStream_t st) {
+  const int grid = grid_for(n, 256, 1024);
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(grid), dim3(256), 0, st, yhat, y, dz, n, scale, part);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, part, grid, loss);
+  return hipGetLastError();
+}
+
+hipError_t mlp_colsum(const __bf16* dz, int rows, int N, float* db, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, st, dz, rows, N, db);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* w, __bf16* wb, const float* g, float* m, float* v, long n, const AdamStep& a,
+                    hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, w, wb, g, m, v, n, a);
+  return hipGetLastError();
+}
+
+}  // namespace pdhcg

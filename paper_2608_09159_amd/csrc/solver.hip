@@ -1230,6 +1230,18 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t reset_cone_failure(hipStream_t st) {
+  const unsigned zero = 0u;
+  return hipMemcpyToSymbolAsync(HIP_SYMBOL(g_cone_fail_count), &zero, sizeof(zero), 0, hipMemcpyHostToDevice,
+                                st);
+}
+
+hipError_t read_cone_failure(double rec[8], unsigned* count) {
+  hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_cone_fail_count), sizeof(unsigned));
+  if (e != hipSuccess) return e;
+  return hipMemcpyFromSymbol(rec, HIP_SYMBOL(g_cone_fail), 8 * sizeof(double));
+}
+
 int batch_grid_limit(bool cones) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;

@@ -15,6 +15,10 @@ hipError_t launch_norm(const double* x, long n, double* part, double* nrm, hipSt
 hipError_t launch_scale(double* x, long n, const double* nrm, hipStream_t st);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t st);
 
+// diagnostics of failed cone root-finding
+hipError_t reset_cone_failure(hipStream_t st);
+hipError_t read_cone_failure(double rec[8], unsigned* count);
+
 // batch solve (one workgroup per instance)
 int batch_grid_limit(bool cones);
 hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t st);

@@ -133,6 +133,20 @@ def test_full_size_fisher_first_iterations():
     trace_parity(p, iters=3, check_every=64)
 
 
+@pytest.mark.parametrize("seed", [26, 31, 41])
+def test_fisher_dual_slack_near_polar(seed):
+    """Fisher instances whose solved exponential-cone dual slacks sit within
+    rounding of the dual cone's boundary: the KKT projection of -s returns
+    ~0 there, and the solve reaches the tolerance (these seeds once ended
+    in a numerical failure)."""
+    p = synth.fisher(seed=seed)
+    g = G.solve(p)
+    cnt, rec = G.last_cone_failure()
+    assert cnt == 0, rec
+    assert g["status"] == "OPTIMAL"
+    recheck_kkt(p, g, 1e-6)
+
+
 def test_full_size_tiny_qp_config_solve():
     p = synth.tiny_qp(0)
     g = G.solve(p)
