@@ -113,6 +113,13 @@ def load(path=None):
     if not os.path.exists(p):
         raise RuntimeError(f"libpdhcg.so not found at {p}; build it with "
                            "`python -m paper_2608_09159_amd.build` (hipcc, gfx950)")
+    # torch bundles its own HIP runtime under the same soname as the one this
+    # library links; loading torch first makes the process use one runtime
+    # (loaded the other way round, torch later finds no GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(p)
     lib.pdhcg_default_settings.argtypes = [C.POINTER(Settings)]
     lib.pdhcg_setup.argtypes = [C.POINTER(ProblemC), C.c_int32, C.POINTER(Settings),
