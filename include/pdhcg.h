@@ -152,8 +152,9 @@ typedef struct {
     int32_t autotune;             /* batches: 1 = choose the lanes-per-row
                                      mapping of the A and A^T products by
                                      timing candidate mappings at setup;
-                                     0 = fixed rule (about 2 nonzeros per
-                                     lane).  Ignored for single problems.     */
+                                     0 = the rule of single problems (fewest
+                                     dependent memory round trips per pass).
+                                     Ignored for single problems.            */
     int32_t tune_iters;           /* outer iterations per autotuner probe (64)*/
     double  fp32_tol;             /* PDHCG_PREC_FP32: tolerance of the FP32
                                      phase; the FP64 polish then restarts at

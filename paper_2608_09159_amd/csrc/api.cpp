@@ -59,6 +59,7 @@ struct Instance {
   double* scratch = nullptr;   // power iteration scratch
   double qmax = 0.0;
   int grid = 1;
+  int lds_bytes = 0;           // dynamic LDS per workgroup for its slice of R
   size_t bar_bytes = 0;
   long n_warm = 0;
 };
@@ -105,6 +106,25 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+// lanes per row minimising the dependent memory round trips of one
+// workgroup's pass over `rows` rows of mean length `mean`: each group of rows
+// costs a row-pointer load plus, per four nonzeros of a lane, a column-index
+// and a gathered-value load
+int pick_lanes(double rows, double mean) {
+  int best = 1;
+  double bc = 1e300;
+  for (int L = 1; L <= 64; L *= 2) {
+    const double passes = std::ceil(std::max(rows, 1.0) / (double)(block_size() / L));
+    const double trips = std::ceil(std::max(mean, 1.0) / (4.0 * L));
+    const double cost = passes * (1.0 + 2.0 * trips) + 0.25 * std::log2((double)L);
+    if (cost < bc) {
+      bc = cost;
+      best = L;
+    }
+  }
+  return best;
+}
 
 int pow2_floor(double v) {
   int L = 1;
@@ -177,6 +197,8 @@ int upload_instance(Handle* h, Instance* I) {
   }
   P.R = H.r > 0 ? B.upload(H.R) : nullptr;
   P.Dm = H.r > 0 ? B.upload(H.D) : nullptr;
+  P.p_diag = H.p_diag ? 1 : 0;
+  P.Pd = H.p_diag ? B.upload(H.pdiag) : nullptr;
   P.A_valf = P.AT_valf = P.P_valf = P.Rf = nullptr;
   if (h->s.precision == PDHCG_PREC_FP32) {
     auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
@@ -251,7 +273,10 @@ int upload_instance(Handle* h, Instance* I) {
   int G = h->s.grid_dim;
   if (G <= 0) {
     long work = std::max<long>(std::max<long>(n, m), 1);
-    long want = (work + (long)block_size() - 1) / (long)block_size();
+    // about two thirds of a workgroup's threads per row or coordinate
+    // (measured: more, smaller workgroups shorten every latency-bound phase)
+    const long per = std::max(1L, (long)block_size() * 2 / 3);
+    long want = (work + per - 1) / per;
     G = (int)std::min<long>(std::max<long>(want, 1), maxg);
   }
   G = std::max(1, std::min(G, maxg));
@@ -307,11 +332,7 @@ int upload_instance(Handle* h, Instance* I) {
     // lanes per row chosen per workgroup from its own rows (about two
     // nonzeros per lane), SOC/RSOC group width from its longest block
     std::vector<unsigned char> lanes(4 * (size_t)G, 1);
-    auto pick = [](double mean) {
-      int L = 1;
-      while (L * 2 <= std::max(1.0, mean / 2.0) && L < 64) L *= 2;
-      return L;
-    };
+    auto pick = [](double rows, double mean) { return pick_lanes(rows, mean); };
     for (int w = 0; w < G; ++w) {
       long nr = pc[w + 1] - pc[w];
       double nz = 0.0;
@@ -319,14 +340,19 @@ int upload_instance(Handle* h, Instance* I) {
         nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
         if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
       }
-      lanes[4 * w + 0] = (unsigned char)(h->s.lanes_at > 0 ? h->s.lanes_at : pick(nr > 0 ? nz / nr : 1.0));
+      lanes[4 * w + 0] = (unsigned char)(h->s.lanes_at > 0 ? h->s.lanes_at : pick((double)nr, nr > 0 ? nz / nr : 1.0));
       long mr = pr[w + 1] - pr[w];
       double mz = mr > 0 ? (double)(H.A.ptr[pr[w + 1]] - H.A.ptr[pr[w]]) / mr : 1.0;
-      lanes[4 * w + 1] = (unsigned char)(h->s.lanes_a > 0 ? h->s.lanes_a : pick(mz));
+      lanes[4 * w + 1] = (unsigned char)(h->s.lanes_a > 0 ? h->s.lanes_a : pick((double)mr, mz));
       int maxdim = 1;
       for (int it = pw[w]; it < pw[w + 1]; ++it) maxdim = std::max(maxdim, H.wave_dim[it]);
       lanes[4 * w + 2] = (unsigned char)(maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64));
     }
+    // the owned columns of R in LDS when the largest slice fits in 64 KiB
+    long maxloc = 0;
+    for (int w = 0; w < G; ++w) maxloc = std::max(maxloc, pc[w + 1] - pc[w]);
+    const size_t rbytes = (size_t)H.r * (size_t)maxloc * sizeof(double);
+    I->lds_bytes = (H.r > 0 && rbytes <= (size_t)64 * 1024) ? (int)rbytes : 0;
     P.part_c = B.upload(pc);
     P.part_r = B.upload(pr);
     P.part_w = B.upload(pw);
@@ -491,6 +517,8 @@ void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D)
   }
   P.R = H.r > 0 ? c.put(H.R) : nullptr;
   P.Dm = H.r > 0 ? c.put(H.D) : nullptr;
+  P.p_diag = H.p_diag ? 1 : 0;
+  P.Pd = H.p_diag ? c.put(H.pdiag) : nullptr;
   P.b = c.put(H.b);
   P.c = c.put(H.c);
   P.qd = c.put(H.qdiag);
@@ -553,8 +581,11 @@ void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D)
   D.y0 = nullptr;
 }
 
-// lanes per row for rows of mean length `mean`: a power of two <= mean/div
-int lanes_rule(double mean, int div) {
+// lanes per row for rows of mean length `mean`: a power of two <= mean/div;
+// div = 0 selects the round-trip model of the single-problem path (with the
+// whole instance on one workgroup)
+int lanes_rule(double rows, double mean, int div) {
+  if (div <= 0) return pick_lanes(rows, mean);
   int L = 1;
   while (L * 2 <= std::max(1.0, mean / div) && L < 64) L *= 2;
   return L;
@@ -568,8 +599,8 @@ void set_lanes(Handle* h, int div_a, int div_at) {
     if (H.P.rows > 0) nz_at = std::max<int64_t>(nz_at, H.P.nnz());
     const double mat = H.n > 0 ? (double)nz_at / H.n : 1.0;
     const double ma = H.m > 0 ? (double)H.A.nnz() / H.m : 1.0;
-    B->desc[i].la = h->s.lanes_at > 0 ? h->s.lanes_at : lanes_rule(mat, div_at);
-    B->desc[i].lr = h->s.lanes_a > 0 ? h->s.lanes_a : lanes_rule(ma, div_a);
+    B->desc[i].la = h->s.lanes_at > 0 ? h->s.lanes_at : lanes_rule((double)H.n, mat, div_at);
+    B->desc[i].lr = h->s.lanes_a > 0 ? h->s.lanes_a : lanes_rule((double)H.m, ma, div_a);
   }
   B->div_a = div_a;
   B->div_at = div_at;
@@ -673,8 +704,8 @@ int setup_batch(Handle* h) {
   B->grid = h->s.grid_dim > 0 ? std::min(h->s.grid_dim, lim) : lim;
   B->grid = std::max(1, std::min(B->grid, count));
 
-  // step sizes: power iteration per instance with the fixed lane rule
-  set_lanes(h, 2, 2);
+  // step sizes: power iteration per instance with the default lane rule
+  set_lanes(h, 0, 0);
   int rc = upload_desc(h, st);
   if (rc != PDHCG_OK) return rc;
   std::vector<double> an(count, h->s.a_norm);
@@ -705,9 +736,9 @@ int setup_batch(Handle* h) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 3.4e38f;
-    int bda = 2, bdat = 2;
-    const int divs_a[] = {1, 2, 4, 8, 16};
-    const int divs_at[] = {1, 2, 4};
+    int bda = 0, bdat = 0;
+    const int divs_a[] = {0, 1, 2, 4, 8, 16};   // 0: the round-trip model
+    const int divs_at[] = {0, 1, 2, 4};
     for (int pass = 0; pass < 2; ++pass) {     // pass 0 warms caches and code
       for (int da : divs_a) {
         for (int dat : divs_at) {
@@ -955,6 +986,7 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   a.T = I->T;
   a.spin_limit = h->spin_limit;
   a.qmax = I->qmax;
+  a.lds_bytes = I->lds_bytes;
   a.profile = h->s.verbose & 8 ? 1 : 0;
   unsigned long long* dpt = nullptr;
   if (a.profile) {

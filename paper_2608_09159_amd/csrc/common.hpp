@@ -41,6 +41,8 @@ struct DevProblem {
   const int64_t* A_ptr;  const int* A_col;  const double* A_val;
   const int64_t* AT_ptr; const int* AT_col; const double* AT_val;
   const int64_t* P_ptr;  const int* P_col;  const double* P_val;  // nullable
+  const double* Pd;      // diag(P^) when p_diag (P u is then Pd * u)
+  int p_diag;
   const double* R;       // r x n row-major (scaled)
   // FP32 copies of the values of A, A^T, P, R (FP32 mode only; else null)
   const float* A_valf; const float* AT_valf; const float* P_valf; const float* Rf;
@@ -142,6 +144,7 @@ struct KArgs {
   long long stop_at;   // return to the host when ktot reaches this
   unsigned long long spin_limit;  // grid-barrier wait bound, wall-clock ticks
   double qmax;         // max_i diag(Q^)_i (first Euclidean BB step)
+  int lds_bytes;       // dynamic LDS per workgroup (R slice; 0 = none)
   int profile;         // accumulate phase timers in ctl->pt and ptimes
   unsigned long long* ptimes;   // [G][PT_COUNT] per-workgroup timers (profile)
 };
@@ -153,6 +156,8 @@ struct Run {
   long long stop_at;             // return when ktot reaches this
   double qmax;                   // max_i diag(Q^)_i (first Euclidean BB step)
   unsigned long long deadline;   // wall-clock tick; 0 = none (checked at checks)
+  void* lds;                     // dynamic LDS for the workgroup's slice of R (nullable)
+  int lds_bytes;
 };
 
 // one instance of a batch: its problem, vectors, trace buffers and control

@@ -250,12 +250,16 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   H.AT = transpose(A);
   H.qdiag.assign(n, 0.0);
   H.q_diag = (r == 0);
+  bool offdiag = false;
   if (hasP)
     for (int64_t i = 0; i < n; ++i)
       for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) {
         if (H.P.col[k] == i) H.qdiag[i] += H.P.val[k];
-        else H.q_diag = false;
+        else offdiag = true;
       }
+  if (offdiag) H.q_diag = false;
+  H.p_diag = hasP && !offdiag;
+  if (H.p_diag) H.pdiag = H.qdiag;   // R's part is added below
   for (int i = 0; i < n && r > 0; ++i) {
     double acc = 0.0;
     for (int a = 0; a < r; ++a) {

@@ -31,6 +31,8 @@ struct HostInstance {
   double nu_b = 1, nu_c = 1;
   double norm_b = 0, norm_c = 0;  // of the original data
   bool q_diag = true;
+  bool p_diag = false;            // P present and diagonal: P u = pdiag * u
+  std::vector<double> pdiag;      // diag(P^) when p_diag
   std::vector<ConeBlock> cones;
   // per-coordinate kind and cone work items
   std::vector<uint8_t> ctype;

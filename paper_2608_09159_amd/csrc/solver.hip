@@ -173,14 +173,29 @@ __device__ __forceinline__ void hw_clear(Lds& L) {
   __syncthreads();
 }
 
+// the dense factor R (r x n, row-major) as read by one workgroup: from its
+// LDS copy of the owned columns [c0, c0 + nl) when there is one, else from
+// global memory.  Every R access of a solve is to an owned column, so a
+// slice that fits in LDS turns r dependent global loads per coordinate into
+// LDS reads.
+template <class MV>
+struct RSrc {
+  const MV* g;
+  long n;
+  const MV* l;     // LDS slice [r][nl] or null
+  long nl, c0;
+  __device__ __forceinline__ MV operator()(int k, long i) const {
+    return l ? l[(size_t)k * nl + (i - c0)] : g[(size_t)k * n + i];
+  }
+};
+
 // wave-uniform: add R[k, i] * val (0 if !active) to the wave's accumulators
 // (the product in the factor's precision, the sums in FP64)
 template <class MV>
-__device__ __forceinline__ void hw_add(Lds& L, const MV* R, long n, int r, long i, double val,
-                                       bool active) {
+__device__ __forceinline__ void hw_add(Lds& L, const RSrc<MV>& R, int r, long i, double val, bool active) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = 0; k < r; ++k) {
-    double t = active ? (double)(R[(size_t)k * n + i] * (MV)val) : 0.0;
+    double t = active ? (double)(R(k, i) * (MV)val) : 0.0;
     t = wave_sum(t);
     if (lane == 0) L.hw[wv][k] += t;
   }
@@ -188,9 +203,9 @@ __device__ __forceinline__ void hw_add(Lds& L, const MV* R, long n, int r, long 
 
 // sum_k R[k, i] ht[k] in increasing k, accumulated in the factor's precision
 template <class MV>
-__device__ __forceinline__ double r_dot(const MV* R, long n, int r, long i, const double* ht) {
+__device__ __forceinline__ double r_dot(const RSrc<MV>& R, int r, long i, const double* ht) {
   MV acc = 0;
-  for (int k = 0; k < r; ++k) acc += R[(size_t)k * n + i] * (MV)ht[k];
+  for (int k = 0; k < r; ++k) acc += R(k, i) * (MV)ht[k];
   return (double)acc;
 }
 
@@ -434,6 +449,18 @@ template <bool CONES, class MV, class Team>
 __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, Ctl* ctl,
                            const Team& T, Lds& L, const Own& own, bool prof) {
   const Bulk<MV> M(P);
+  // LDS copy of the owned columns of R (bulk precision); the FP64 reads of
+  // an FP32 run (start, checks) stay in global memory
+  const long nloc = own.c1 - own.c0;
+  MV* rl = nullptr;
+  if (A.lds && P.r > 0 && (size_t)P.r * (size_t)nloc * sizeof(MV) <= (size_t)A.lds_bytes) {
+    rl = reinterpret_cast<MV*>(A.lds);
+    for (long e = threadIdx.x; e < (long)P.r * nloc; e += BLOCK)
+      rl[e] = M.R[(size_t)(e / nloc) * P.n + own.c0 + e % nloc];
+  }
+  const RSrc<MV> RB{M.R, (long)P.n, rl, nloc, own.c0};
+  const RSrc<double> R64{P.R, (long)P.n, sizeof(MV) == sizeof(double) ? reinterpret_cast<const double*>(rl) : nullptr,
+                         nloc, own.c0};
   const int tid = threadIdx.x;
   const int rank = T.rank, G = T.size;
   const long n = P.n, m = P.m;
@@ -482,14 +509,14 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       bool el = act && P.ctype[i] != CT_CONE;
       double x = el ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
       if (el) { V.x[i] = x; V.ax[i] = x; }
-      hw_add(L, P.R, n, r, i, x, el);
+      hw_add(L, R64, r, i, x, el);
     });
     if (has_items) {
       project_items(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
       for_item_coords(P, IT, [&](long i, bool act) {
         double x = act ? V.zb[i] : 0.0;
         if (act) { V.x[i] = x; V.ax[i] = x; }
-        hw_add(L, P.R, n, r, i, x, act);
+        hw_add(L, R64, r, i, x, act);
       });
     }
     hw_store(L, r, part, G, rank);
@@ -547,7 +574,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     tmark(L, prof, PT_P1);
     spmv_range(P.AT_ptr, P.AT_col, M.AT, V.y, V.t1, c0, c1, La);
     if (!P.q_diag) {
-      if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, M.Pv, V.x, V.t2, c0, c1, La);
+      if (P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, M.Pv, V.x, V.t2, c0, c1, La);
       make_ht(L, P, L.C.hx);
     } else {
       __syncthreads();
@@ -574,8 +601,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         if (act) {
           const double xi = V.x[i];
           const double vi = xi + tau * V.t1[i];
-          const double ru = r_dot(M.R, n, r, i, L.ht);
-          const double pu = P.P_ptr ? V.t2[i] : 0.0;
+          const double ru = r_dot(RB, r, i, L.ht);
+          const double pu = P.p_diag ? P.Pd[i] * xi : (P.P_ptr ? V.t2[i] : 0.0);
           const double g0 = pu + ru + P.c[i] + (xi - vi) / tau;
           const double z = xi - alpha0 * g0 / Mq(i);
           V.v[i] = vi;
@@ -590,7 +617,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.zb[i] = z;
           }
         }
-        hw_add(L, M.R, n, r, i, un, el);
+        hw_add(L, RB, r, i, un, el);
       });
       if (has_items) {
         __syncthreads();
@@ -603,7 +630,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             const double dd = un - V.up[i];
             d2 += dd * dd;
           }
-          hw_add(L, M.R, n, r, i, un, act);
+          hw_add(L, RB, r, i, un, act);
         });
       }
       const int sl[1] = {SL_DELTA2};
@@ -626,14 +653,14 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       while (!done && jcount < jmax) {
         // ---- P3: gradient at u, BB reductions
         tmark(L, prof, PT_P3);
-        if (P.P_ptr) spmv_range(P.P_ptr, P.P_col, M.Pv, V.u, V.t2, c0, c1, La);
+        if (P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, M.Pv, V.u, V.t2, c0, c1, La);
         make_ht(L, P, L.hu);
         double acc[3] = {0.0, 0.0, 0.0};
         for_range(c0, c1, [&](long i, bool act) {
           if (!act) return;
-          const double ru = r_dot(M.R, n, r, i, L.ht);
+          const double ru = r_dot(RB, r, i, L.ht);
           const double ui = V.u[i];
-          const double pu = P.P_ptr ? V.t2[i] : 0.0;
+          const double pu = P.p_diag ? P.Pd[i] * ui : (P.P_ptr ? V.t2[i] : 0.0);
           const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
           const double si = ui - V.up[i];
           const double dg = gc - V.gp[i];
@@ -671,7 +698,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.gp[i] = gi;
             V.u[i] = un;
           }
-          hw_add(L, M.R, n, r, i, un, el);
+          hw_add(L, RB, r, i, un, el);
         });
         if (has_items) {
           PROJ(project_items(P, IT, !jac,
@@ -687,7 +714,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
               V.gp[i] = V.g[i];
               V.u[i] = un;
             }
-            hw_add(L, M.R, n, r, i, un, act);
+            hw_add(L, RB, r, i, un, act);
           });
         }
         {
@@ -756,7 +783,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
-        if (!check) hw_add(L, M.R, n, r, i, xn, act);
+        if (!check) hw_add(L, RB, r, i, xn, act);
       });
       if (check) {
         const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
@@ -804,7 +831,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       // dual slack s = Q w + c - A^T w_y on own coordinates; R^ w_x is the
       // last inner R^ u (diagonal Q has r = 0)
       spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, c0, c1, La);
-      if (!P.q_diag && P.P_ptr) spmv_range(P.P_ptr, P.P_col, P.P_val, W, V.t2, c0, c1, La);
+      if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, W, V.t2, c0, c1, La);
       if (!P.q_diag) make_ht(L, P, L.hu);
       else __syncthreads();
       double acc[2] = {0.0, 0.0};
@@ -815,8 +842,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         if (P.q_diag) {
           qw = P.qd[i] * wi;
         } else {
-          qw = P.P_ptr ? V.t2[i] : 0.0;
-          qw += r_dot(P.R, n, r, i, L.ht);
+          qw = P.p_diag ? P.Pd[i] * wi : (P.P_ptr ? V.t2[i] : 0.0);
+          qw += r_dot(R64, r, i, L.ht);
         }
         const double si = qw + P.c[i] - V.t1[i];
         acc[0] += wi * qw;                               // SL_XQX
@@ -918,7 +945,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
-        if (!restart) hw_add(L, M.R, n, r, i, xn, act);
+        if (!restart) hw_add(L, RB, r, i, xn, act);
       });
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
@@ -975,7 +1002,8 @@ __device__ void solve_body(const KArgs& A) {
   own.la = P.part_lanes[4 * rank + 0];
   own.lr = P.part_lanes[4 * rank + 1];
   GridTeam T{A.bar, A.spin_limit, rank, G};
-  const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull};
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull, A.lds_bytes > 0 ? dyn_lds : nullptr, A.lds_bytes};
   run_solver<true, MV>(run, P, A.V, A.ctl, T, L, own, prof);
   tmark(L, prof, PT_INIT);
   __syncthreads();
@@ -1089,7 +1117,7 @@ __device__ void batch_body(const BatchArgs& B) {
       own.it = Items{0, D.P.n_wave, 0, D.P.n_lane, D.lg};
       own.la = D.la;
       own.lr = D.lr;
-      const Run run{&B.S, &D.T, B.stop_at, D.qmax, deadline};
+      const Run run{&B.S, &D.T, B.stop_at, D.qmax, deadline, nullptr, 0};
       run_solver<CONES, double>(run, D.P, D.V, D.ctl, SoloTeam{}, L, own, prof);
       tmark(L, prof, PT_INIT);
       __syncthreads();
@@ -1175,7 +1203,7 @@ hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stre
   KArgs a = args;
   void* params[] = {&a};
   const void* k = fp32 ? (const void*)solve_kernel_f32 : (const void*)solve_kernel;
-  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BLOCK), params, 0, stream);
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BLOCK), params, (size_t)args.lds_bytes, stream);
 }
 
 hipError_t max_coop_grid(int* out) {
