@@ -111,10 +111,10 @@ struct Batch {
 // workgroup's pass over `rows` rows of mean length `mean`: each group of rows
 // costs a row-pointer load plus, per four nonzeros of a lane, a column-index
 // and a gathered-value load
-int pick_lanes(double rows, double mean) {
+int pick_lanes(double rows, double mean, int maxL = 64) {
   int best = 1;
   double bc = 1e300;
-  for (int L = 1; L <= 64; L *= 2) {
+  for (int L = 1; L <= maxL; L = (L == 64 ? block_size() : 2 * L)) {
     const double passes = std::ceil(std::max(rows, 1.0) / (double)(block_size() / L));
     const double trips = std::ceil(std::max(mean, 1.0) / (4.0 * L));
     const double cost = passes * (1.0 + 2.0 * trips) + 0.25 * std::log2((double)L);
@@ -287,22 +287,111 @@ int upload_instance(Handle* h, Instance* I) {
   {
     std::vector<long> pc(G + 1, 0), pr(G + 1, 0);
     std::vector<int> pw(G + 1, 0), pl(G + 1, 0);
-    auto split = [&](const std::vector<std::pair<long, double>>& units, long total_items,
-                     std::vector<long>& out) {
-      double total = 0.0;
-      for (const auto& u : units) total += u.second;
-      out[0] = 0;
-      int kk = 1;
-      double cum = 0.0;
-      for (const auto& u : units) {
-        cum += u.second;
-        while (kk < G && cum >= total * kk / G) out[kk++] = u.first;   // u.first = end index
+    // split into G contiguous ranges.  A unit flagged heavy (it holds a row
+    // far longer than the rest) gets a workgroup of its own, so its lanes are
+    // chosen for it alone; the other workgroups are shared among the light
+    // segments between heavy units in proportion to their weight (at least
+    // one per nonempty segment), and each segment is cut by cumulative
+    // weight.  Without heavy units this is the plain cumulative split.
+    auto split = [&](const std::vector<std::pair<long, double>>& units, const std::vector<char>& heavy_u,
+                     long total_items, std::vector<long>& out) {
+      struct Seg { size_t a, b; bool heavy; double w; int k; };
+      std::vector<Seg> segs;
+      double wlight = 0.0;
+      for (size_t i = 0; i < units.size();) {
+        if (heavy_u[i]) {
+          segs.push_back({i, i + 1, true, units[i].second, 1});
+          ++i;
+          continue;
+        }
+        size_t j = i;
+        double w = 0.0;
+        while (j < units.size() && !heavy_u[j]) w += units[j++].second;
+        segs.push_back({i, j, false, w, 0});
+        wlight += w;
+        i = j;
       }
-      while (kk <= G) out[kk++] = total_items;
+      int nheavy = 0, nlight = 0;
+      for (const auto& s : segs) (s.heavy ? nheavy : nlight) += 1;
+      int avail = G - nheavy;
+      if (nheavy == 0 || avail < nlight) {
+        // plain cumulative split (also the fallback when there are too many
+        // heavy units for dedicated workgroups)
+        double total = 0.0;
+        for (const auto& u : units) total += u.second;
+        out[0] = 0;
+        int kk = 1;
+        double cum = 0.0;
+        for (const auto& u : units) {
+          cum += u.second;
+          while (kk < G && cum >= total * kk / G) out[kk++] = u.first;
+        }
+        while (kk <= G) out[kk++] = total_items;
+        out[G] = total_items;
+        return;
+      }
+      // proportional shares with at least one workgroup per light segment
+      int given = 0;
+      for (auto& s : segs)
+        if (!s.heavy) {
+          s.k = std::max(1, (int)std::floor(avail * s.w / std::max(wlight, 1e-300)));
+          given += s.k;
+        }
+      while (given > avail) {          // take back from the largest shares
+        Seg* big = nullptr;
+        for (auto& s : segs)
+          if (!s.heavy && s.k > 1 && (!big || s.w / s.k < big->w / big->k)) big = &s;
+        if (!big) break;
+        big->k -= 1;
+        given -= 1;
+      }
+      while (given < avail) {          // hand out the rest to the heaviest per workgroup
+        Seg* big = nullptr;
+        for (auto& s : segs)
+          if (!s.heavy && (!big || s.w / s.k > big->w / big->k)) big = &s;
+        if (!big) break;
+        big->k += 1;
+        given += 1;
+      }
+      int kk = 0;
+      out[0] = 0;
+      for (const auto& s : segs) {
+        const long seg_end = units[s.b - 1].first;
+        if (s.heavy || s.k == 1) {
+          out[++kk] = seg_end;
+          continue;
+        }
+        double cum = 0.0;
+        int made = 0;
+        for (size_t u = s.a; u < s.b && made < s.k - 1; ++u) {
+          cum += units[u].second;
+          while (made < s.k - 1 && cum >= s.w * (made + 1) / s.k) {
+            out[++kk] = units[u].first;
+            ++made;
+          }
+        }
+        while (made < s.k - 1) {
+          out[++kk] = seg_end;
+          ++made;
+        }
+        out[++kk] = seg_end;
+      }
+      while (kk < G) out[++kk] = total_items;
       out[G] = total_items;
     };
     std::vector<std::pair<long, double>> cu;
+    std::vector<char> cheavy;
     cu.reserve(n);
+    cheavy.reserve(n);
+    // a coordinate whose A^T or P row has at least 4096 nonzeros and more
+    // than 5% of a workgroup's share of all of them
+    const double rownz_total = (double)H.AT.nnz() + (double)(H.P.rows > 0 ? H.P.nnz() : 0);
+    const double heavy_nz = std::max(4096.0, 0.05 * rownz_total / G);
+    auto rownz = [&](long i) {
+      double z = (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+      if (H.P.rows > 0) z = std::max(z, (double)(H.P.ptr[i + 1] - H.P.ptr[i]));
+      return z;
+    };
     for (const auto& cb : H.cones) {
       auto wcoord = [&](long i) {
         double w = 2.0 + (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]) + H.r;
@@ -310,19 +399,26 @@ int upload_instance(Handle* h, Instance* I) {
         return w;
       };
       if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
-        for (long i = cb.start; i < cb.start + cb.dim; ++i) cu.emplace_back(i + 1, wcoord(i));
+        for (long i = cb.start; i < cb.start + cb.dim; ++i) {
+          cu.emplace_back(i + 1, wcoord(i));
+          cheavy.push_back(rownz(i) > heavy_nz);
+        }
       } else {
-        double w = 0.0;
-        for (long i = cb.start; i < cb.start + cb.dim; ++i) w += wcoord(i) + 16.0;
+        double w = 0.0, zmax = 0.0;
+        for (long i = cb.start; i < cb.start + cb.dim; ++i) {
+          w += wcoord(i) + 16.0;
+          zmax = std::max(zmax, rownz(i));
+        }
         if (cb.type == PDHCG_CONE_EXP || cb.type == PDHCG_CONE_POW) w += 400.0;
         cu.emplace_back((long)cb.start + cb.dim, w);
+        cheavy.push_back(zmax > heavy_nz);
       }
     }
-    split(cu, n, pc);
+    split(cu, cheavy, n, pc);
     std::vector<std::pair<long, double>> ru;
     ru.reserve(m);
     for (long l = 0; l < m; ++l) ru.emplace_back(l + 1, 2.0 + (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
-    split(ru, m, pr);
+    split(ru, std::vector<char>(ru.size(), 0), m, pr);
     for (int w = 0; w <= G; ++w) {
       pw[w] = (int)(std::lower_bound(H.wave_start.begin(), H.wave_start.end(), (int)std::min<long>(pc[w], n)) -
                     H.wave_start.begin());
@@ -331,8 +427,7 @@ int upload_instance(Handle* h, Instance* I) {
     }
     // lanes per row chosen per workgroup from its own rows (about two
     // nonzeros per lane), SOC/RSOC group width from its longest block
-    std::vector<unsigned char> lanes(4 * (size_t)G, 1);
-    auto pick = [](double rows, double mean) { return pick_lanes(rows, mean); };
+    std::vector<unsigned short> lanes(4 * (size_t)G, 1);
     for (int w = 0; w < G; ++w) {
       long nr = pc[w + 1] - pc[w];
       double nz = 0.0;
@@ -340,13 +435,14 @@ int upload_instance(Handle* h, Instance* I) {
         nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
         if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
       }
-      lanes[4 * w + 0] = (unsigned char)(h->s.lanes_at > 0 ? h->s.lanes_at : pick((double)nr, nr > 0 ? nz / nr : 1.0));
+      lanes[4 * w + 0] = (unsigned short)(h->s.lanes_at > 0 ? h->s.lanes_at
+                                                          : pick_lanes((double)nr, nr > 0 ? nz / nr : 1.0, block_size()));
       long mr = pr[w + 1] - pr[w];
       double mz = mr > 0 ? (double)(H.A.ptr[pr[w + 1]] - H.A.ptr[pr[w]]) / mr : 1.0;
-      lanes[4 * w + 1] = (unsigned char)(h->s.lanes_a > 0 ? h->s.lanes_a : pick((double)mr, mz));
+      lanes[4 * w + 1] = (unsigned short)(h->s.lanes_a > 0 ? h->s.lanes_a : pick_lanes((double)mr, mz));
       int maxdim = 1;
       for (int it = pw[w]; it < pw[w + 1]; ++it) maxdim = std::max(maxdim, H.wave_dim[it]);
-      lanes[4 * w + 2] = (unsigned char)(maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64));
+      lanes[4 * w + 2] = (unsigned short)(maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64));
     }
     // the owned columns of R in LDS when the largest slice fits in 64 KiB
     long maxloc = 0;

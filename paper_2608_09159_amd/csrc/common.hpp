@@ -68,7 +68,8 @@ struct DevProblem {
   const long* part_r;
   const int* part_w;
   const int* part_l;
-  const unsigned char* part_lanes;  // per workgroup: lanes for A^T/P rows, A rows,
+  const unsigned short* part_lanes;  // per workgroup: lanes for A^T/P rows (up to
+                                     // 512: the whole workgroup), A rows,
                                     // SOC/RSOC group width, pad
 };
 

@@ -271,9 +271,38 @@ __device__ __forceinline__ double spmv_row(const int64_t* ptr, const int* col, c
 
 // rows [r0, r1) of a CSR matrix times x into out, Lw lanes per row, this
 // workgroup only
+// rows [r0, r1) one at a time, each by the whole workgroup: a strided pass
+// of all 512 threads and a fixed-order block sum.  For rows far longer than
+// the rest, which the partition puts alone on their workgroup.  Kept out of
+// line: inlined into the solver it would cost registers everywhere.
+template <class MV>
+__device__ __noinline__ void spmv_rows_block(const int64_t* ptr, const int* col, const MV* val,
+                                             const double* x, double* out, long r0, long r1) {
+  __shared__ double red[NWAVE];
+  for (long row = r0; row < r1; ++row) {
+    MV acc = 0;
+    const int64_t e = ptr[row + 1];
+#pragma unroll 8
+    for (int64_t k = ptr[row] + threadIdx.x; k < e; k += BLOCK) acc += val[k] * (MV)x[col[k]];
+    const double sw = wave_sum((double)acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NWAVE; ++w) t += red[w];
+      out[row] = t;
+    }
+    __syncthreads();
+  }
+}
+
 template <class MV>
 __device__ void spmv_range(const int64_t* ptr, const int* col, const MV* val, const double* x,
                            double* out, long r0, long r1, int Lw) {
+  if (Lw >= BLOCK) {
+    spmv_rows_block(ptr, col, val, x, out, r0, r1);
+    return;
+  }
   const int groups = BLOCK / Lw;
   const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
   for (long base = r0; base < r1; base += groups) {
