@@ -393,9 +393,13 @@ int upload_instance(Handle* h, Instance* I) {
       return z;
     };
     for (const auto& cb : H.cones) {
+      // per-coordinate work of one outer iteration: the A^T row once, the
+      // elementwise work, P row (unless P is diagonal) and factor columns
+      // once per prox step (about fq of them for a general Q)
+      const double fq = H.q_diag ? 1.0 : 3.0;
       auto wcoord = [&](long i) {
-        double w = 2.0 + (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]) + H.r;
-        if (H.P.rows > 0) w += (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
+        double w = fq * (2.0 + H.r) + (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+        if (H.P.rows > 0 && !H.p_diag) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
         return w;
       };
       if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
@@ -406,10 +410,10 @@ int upload_instance(Handle* h, Instance* I) {
       } else {
         double w = 0.0, zmax = 0.0;
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
-          w += wcoord(i) + 16.0;
+          w += wcoord(i) + 16.0 * fq;
           zmax = std::max(zmax, rownz(i));
         }
-        if (cb.type == PDHCG_CONE_EXP || cb.type == PDHCG_CONE_POW) w += 400.0;
+        if (cb.type == PDHCG_CONE_EXP || cb.type == PDHCG_CONE_POW) w += 400.0 * fq;
         cu.emplace_back((long)cb.start + cb.dim, w);
         cheavy.push_back(zmax > heavy_nz);
       }
@@ -449,6 +453,44 @@ int upload_instance(Handle* h, Instance* I) {
     for (int w = 0; w < G; ++w) maxloc = std::max(maxloc, pc[w + 1] - pc[w]);
     const size_t rbytes = (size_t)H.r * (size_t)maxloc * sizeof(double);
     I->lds_bytes = (H.r > 0 && rbytes <= (size_t)64 * 1024) ? (int)rbytes : 0;
+    // skewed A^T row lengths (some row of a workgroup more than 16 times its
+    // mean and longer than 64): order each workgroup's rows by length class
+    // (<= 16, 64, 256, 1024 nonzeros, longer), run with 1, 4, 16, 64 and 512
+    // lanes per row
+    P.at_perm = nullptr;
+    P.at_seg = nullptr;
+    {
+      bool skew = false;
+      for (int w = 0; w < G && !skew; ++w) {
+        const long nr = pc[w + 1] - pc[w];
+        if (nr <= 0) continue;
+        const double mean = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]) / nr;
+        for (long i = pc[w]; i < pc[w + 1]; ++i) {
+          const double z = (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+          if (z > 64.0 && z > 16.0 * mean) { skew = true; break; }
+        }
+      }
+      if (skew && h->s.lanes_at <= 0) {
+        constexpr int NC = 5;
+        std::vector<int> perm(n), seg((size_t)(NC + 1) * G);
+        for (int w = 0; w < G; ++w) {
+          std::vector<std::vector<int>> cls(NC);
+          for (long i = pc[w]; i < pc[w + 1]; ++i) {
+            const long z = H.AT.ptr[i + 1] - H.AT.ptr[i];
+            const int c = z <= 16 ? 0 : (z <= 64 ? 1 : (z <= 256 ? 2 : (z <= 1024 ? 3 : 4)));
+            cls[c].push_back((int)i);
+          }
+          long pos = pc[w];
+          for (int c = 0; c < NC; ++c) {
+            seg[(size_t)(NC + 1) * w + c] = (int)pos;
+            for (int i : cls[c]) perm[pos++] = i;
+          }
+          seg[(size_t)(NC + 1) * w + NC] = (int)pos;
+        }
+        P.at_perm = B.upload(perm);
+        P.at_seg = B.upload(seg);
+      }
+    }
     P.part_c = B.upload(pc);
     P.part_r = B.upload(pr);
     P.part_w = B.upload(pw);

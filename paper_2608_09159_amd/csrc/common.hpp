@@ -68,6 +68,10 @@ struct DevProblem {
   const long* part_r;
   const int* part_w;
   const int* part_l;
+  // A^T rows of each workgroup grouped by length class (skewed row lengths
+  // only; else null): at_perm[n], at_seg[(classes + 1) * G]
+  const int* at_perm;
+  const int* at_seg;
   const unsigned short* part_lanes;  // per workgroup: lanes for A^T/P rows (up to
                                      // 512: the whole workgroup), A rows,
                                     // SOC/RSOC group width, pad

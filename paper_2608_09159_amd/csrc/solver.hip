@@ -313,6 +313,37 @@ __device__ void spmv_range(const int64_t* ptr, const int* col, const MV* val, co
   }
 }
 
+// A^T rows of this workgroup in length classes (rows with skewed lengths):
+// perm lists the workgroup's rows grouped by class, seg[c]..seg[c+1] the
+// positions of class c; class c runs with kClassLanes[c] lanes per row (the
+// last class with the whole workgroup), so no lane walks a row much longer
+// than its neighbours'.  Each row's sum keeps the order of spmv_row.
+constexpr int kClasses = 5;
+__device__ constexpr int kClassLanes[kClasses] = {1, 4, 16, 64, BLOCK};
+
+template <class MV>
+__device__ __noinline__ void spmv_classes(const int64_t* ptr, const int* col, const MV* val, const double* x,
+                             double* out, const int* perm, const int* seg) {
+  for (int c = 0; c < kClasses; ++c) {
+    const int s0 = seg[c], s1 = seg[c + 1];
+    if (s0 >= s1) continue;
+    const int Lw = kClassLanes[c];
+    if (Lw >= BLOCK) {
+      for (int q = s0; q < s1; ++q) spmv_rows_block(ptr, col, val, x, out, (long)perm[q], (long)perm[q] + 1);
+      continue;
+    }
+    const int groups = BLOCK / Lw;
+    const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
+    for (int base = s0; base < s1; base += groups) {
+      const int q = base + gid;
+      const bool act = q < s1;
+      const long row = act ? (long)perm[q] : 0;
+      const double v = spmv_row(ptr, col, val, x, row, sub, Lw, act);
+      if (act && sub == 0) out[row] = v;
+    }
+  }
+}
+
 // wave-uniform loop over the coordinates [c0, c1): f(i, active)
 template <class F>
 __device__ __forceinline__ void for_range(long c0, long c1, F f) {
@@ -472,6 +503,8 @@ struct Own {
   long c0, c1, r0, r1;
   Items it;
   int la, lr;   // lanes per row of A^T / P (own coordinates) and of A (own rows)
+  const int* atperm;   // A^T rows in length classes (null: plain ranges)
+  const int* atseg;
 };
 
 template <bool CONES, class MV, class Team>
@@ -601,7 +634,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
 
     // -------------------------------------------------------------- P1
     tmark(L, prof, PT_P1);
-    spmv_range(P.AT_ptr, P.AT_col, M.AT, V.y, V.t1, c0, c1, La);
+    if (own.atperm) spmv_classes(P.AT_ptr, P.AT_col, M.AT, V.y, V.t1, own.atperm, own.atseg);
+    else spmv_range(P.AT_ptr, P.AT_col, M.AT, V.y, V.t1, c0, c1, La);
     if (!P.q_diag) {
       if (P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, M.Pv, V.x, V.t2, c0, c1, La);
       make_ht(L, P, L.C.hx);
@@ -859,7 +893,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     {
       // dual slack s = Q w + c - A^T w_y on own coordinates; R^ w_x is the
       // last inner R^ u (diagonal Q has r = 0)
-      spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, c0, c1, La);
+      if (own.atperm) spmv_classes(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, own.atperm, own.atseg);
+      else spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, c0, c1, La);
       if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, W, V.t2, c0, c1, La);
       if (!P.q_diag) make_ht(L, P, L.hu);
       else __syncthreads();
@@ -1030,6 +1065,8 @@ __device__ void solve_body(const KArgs& A) {
                  (int)P.part_lanes[4 * rank + 2]};
   own.la = P.part_lanes[4 * rank + 0];
   own.lr = P.part_lanes[4 * rank + 1];
+  own.atperm = P.at_perm;
+  own.atseg = P.at_perm ? P.at_seg + (kClasses + 1) * rank : nullptr;
   GridTeam T{A.bar, A.spin_limit, rank, G};
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull, A.lds_bytes > 0 ? dyn_lds : nullptr, A.lds_bytes};
@@ -1146,6 +1183,8 @@ __device__ void batch_body(const BatchArgs& B) {
       own.it = Items{0, D.P.n_wave, 0, D.P.n_lane, D.lg};
       own.la = D.la;
       own.lr = D.lr;
+      own.atperm = nullptr;
+      own.atseg = nullptr;
       const Run run{&B.S, &D.T, B.stop_at, D.qmax, deadline, nullptr, 0};
       run_solver<CONES, double>(run, D.P, D.V, D.ctl, SoloTeam{}, L, own, prof);
       tmark(L, prof, PT_INIT);

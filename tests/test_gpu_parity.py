@@ -55,6 +55,13 @@ def test_iterate_parity_lane_mappings(lanes):
                  lanes_at=lanes, lanes_a=lanes, grid_dim=3)
 
 
+def test_iterate_parity_skewed_columns():
+    """Power-law column degrees (the large sparse QP family at n = 60,000):
+    the longest A^T rows get workgroups of their own (whole-workgroup rows)
+    and the others run in length classes."""
+    trace_parity(synth.large_sparse_qp(seed=1, n=60_000, m=30_000), iters=20)
+
+
 def test_iterate_parity_edge_cones():
     trace_parity(edge_cone_problem())
     trace_parity(edge_cone_problem(1), grid_dim=3)
