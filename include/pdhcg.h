@@ -160,6 +160,12 @@ typedef struct {
                                      phase; the FP64 polish then restarts at
                                      its candidate and runs to tol
                                      (<= 0: 10 * tol)                         */
+    int32_t interleave;           /* 1: on the device, interleave the cone
+                                     blocks with the FREE/R+ coordinates so
+                                     every workgroup gets a mix of both kinds
+                                     of work (inputs, outputs, traces and
+                                     scalings stay in the caller's order);
+                                     0 (default): the caller's order         */
 } pdhcg_settings;
 
 typedef struct {

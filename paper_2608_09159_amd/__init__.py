@@ -66,7 +66,8 @@ class Settings(C.Structure):
                 ("grid_dim", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
                 ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
-                ("tune_iters", C.c_int32), ("fp32_tol", C.c_double)]
+                ("tune_iters", C.c_int32), ("fp32_tol", C.c_double),
+                ("interleave", C.c_int32)]
 
 
 class ResultC(C.Structure):

@@ -585,8 +585,9 @@ void finish_result(const HostInstance& H, const Ctl& c, int status, const double
   res->omega = c.omega;
   res->a_norm = 0.998 / eta;
   res->setup_s = setup_s;
+  const bool pm = !H.perm.empty();   // internal coordinate j is the caller's perm[j]
   if (res->x)
-    for (long i = 0; i < n; ++i) res->x[i] = H.nu_b * wx[i] / H.Sx[i];
+    for (long i = 0; i < n; ++i) res->x[pm ? H.perm[i] : i] = H.nu_b * wx[i] / H.Sx[i];
   if (res->y)
     for (long l = 0; l < m; ++l) res->y[l] = H.nu_c * H.Sy[l] * wy[l];
   if (res->s) {
@@ -607,7 +608,7 @@ void finish_result(const HostInstance& H, const Ctl& c, int status, const double
     for (long i = 0; i < n; ++i) {
       double aty = 0.0;
       for (int64_t k = H.AT.ptr[i]; k < H.AT.ptr[i + 1]; ++k) aty += H.AT.val[k] * wy[H.AT.col[k]];
-      res->s[i] = H.nu_c * H.Sx[i] * (q[i] + H.c[i] - aty);
+      res->s[pm ? H.perm[i] : i] = H.nu_c * H.Sx[i] * (q[i] + H.c[i] - aty);
     }
   }
 }
@@ -987,6 +988,7 @@ int pdhcg_default_settings(pdhcg_settings* s) {
   s->autotune = 1;
   s->tune_iters = 64;
   s->fp32_tol = 0.0;
+  s->interleave = 0;
   return PDHCG_OK;
 }
 
@@ -1096,7 +1098,7 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   std::vector<double> tmp;
   if (x0) {
     tmp.resize(n);
-    for (long i = 0; i < n; ++i) tmp[i] = H.Sx[i] * x0[i] / H.nu_b;
+    for (long i = 0; i < n; ++i) tmp[i] = H.Sx[i] * x0[H.perm.empty() ? i : H.perm[i]] / H.nu_b;
     HIPCHK(hipMemcpyAsync(I->V.zb, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
   } else {
     HIPCHK(launch_fill(I->V.zb, n, 0.0, st));
@@ -1232,7 +1234,7 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
     const double* x0 = x0s ? x0s[i] : nullptr;
     const double* y0 = y0s ? y0s[i] : nullptr;
     if (x0)
-      for (long j = 0; j < H.n; ++j) px[B->offx[i] + j] = H.Sx[j] * x0[j] / H.nu_b;
+      for (long j = 0; j < H.n; ++j) px[B->offx[i] + j] = H.Sx[j] * x0[H.perm.empty() ? j : H.perm[j]] / H.nu_b;
     if (y0)
       for (long l = 0; l < H.m; ++l) py[B->offy[i] + l] = y0[l] / (H.nu_c * H.Sy[l]);
     const double* want_x = x0 ? B->d_x0 + B->offx[i] : nullptr;
@@ -1347,6 +1349,17 @@ int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {
   if (!cp(t->x, T.x, rec * n) || !cp(t->wx, T.wx, rec * n) || !cp(t->y, T.y, rec * m) ||
       !cp(t->wy, T.wy, rec * m))
     return PDHCG_E_HIP;
+  if (!I->H.perm.empty()) {   // primal slices back to the caller's order
+    std::vector<double> row(n);
+    for (double* base : {t->x, t->wx}) {
+      if (!base) continue;
+      for (long k = 0; k < rec; ++k) {
+        double* v = base + (size_t)k * n;
+        for (long j = 0; j < n; ++j) row[I->H.perm[j]] = v[j];
+        std::copy(row.begin(), row.end(), v);
+      }
+    }
+  }
   std::vector<double> sc(rec * 8);
   if (!cp(sc.data(), T.sc, rec * 8)) return PDHCG_E_HIP;
   for (long k = 0; k < rec; ++k) {
@@ -1368,7 +1381,8 @@ int pdhcg_get_scaling(void* hv, int32_t inst, double* Sx, double* Sy, double* nu
   Handle* h = (Handle*)hv;
   if (!h || inst < 0 || inst >= (int)h->inst.size()) return PDHCG_E_ARG;
   const Instance* I = h->inst[inst];
-  if (Sx) std::copy(I->H.Sx.begin(), I->H.Sx.end(), Sx);
+  if (Sx)
+    for (size_t j = 0; j < I->H.Sx.size(); ++j) Sx[I->H.perm.empty() ? j : (size_t)I->H.perm[j]] = I->H.Sx[j];
   if (Sy) std::copy(I->H.Sy.begin(), I->H.Sy.end(), Sy);
   if (nu_b) *nu_b = I->H.nu_b;
   if (nu_c) *nu_c = I->H.nu_c;

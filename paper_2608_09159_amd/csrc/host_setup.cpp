@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <numeric>
 
 namespace pdhcg {
@@ -82,6 +83,113 @@ double norm2(const std::vector<double>& v) {
   double s = 0.0;
   for (double x : v) s += x * x;
   return std::sqrt(s);
+}
+
+// Interleave the cone blocks with the elementwise (FREE / R+) coordinates,
+// and the cone types with each other, each in proportion to its count, so
+// that contiguous ownership ranges mix projection and elementwise work.
+// Renumbers everything indexed by coordinates (columns of A, rows and
+// columns of P, columns of R, c, S_x, the cone list) and records the
+// permutation; a no-op unless both kinds are present.
+void interleave(HostInstance& H) {
+  H.perm.clear();
+  const int n = H.n;
+  struct Unit { int start, dim, type; double alpha; double key; };
+  std::vector<Unit> plain, cone;
+  for (const auto& cb : H.cones) {
+    if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
+      for (int i = cb.start; i < cb.start + cb.dim; ++i) plain.push_back({i, 1, cb.type, 0.0, 0.0});
+    } else {
+      cone.push_back({cb.start, cb.dim, cb.type, cb.alpha, 0.0});
+    }
+  }
+  if (plain.empty() || cone.empty()) return;
+  // cone types mixed: key = (rank within the type + 1/2) / count of the type
+  int cnt[8] = {0}, seen[8] = {0};
+  for (const auto& u : cone) cnt[u.type]++;
+  for (auto& u : cone) u.key = (seen[u.type]++ + 0.5) / cnt[u.type];
+  std::stable_sort(cone.begin(), cone.end(), [](const Unit& a, const Unit& b) { return a.key < b.key; });
+  for (size_t k = 0; k < cone.size(); ++k) cone[k].key = (k + 0.5) / cone.size();
+  for (size_t k = 0; k < plain.size(); ++k) plain[k].key = (k + 0.5) / plain.size();
+  std::vector<Unit> all;
+  all.reserve(plain.size() + cone.size());
+  std::merge(plain.begin(), plain.end(), cone.begin(), cone.end(), std::back_inserter(all),
+             [](const Unit& a, const Unit& b) { return a.key < b.key; });
+  // new order and the renumbered cone list (runs of one elementwise type
+  // merge into one block)
+  std::vector<int> perm;
+  perm.reserve(n);
+  std::vector<ConeBlock> cones;
+  for (const auto& u : all) {
+    const int ns = (int)perm.size();
+    for (int j = 0; j < u.dim; ++j) perm.push_back(u.start + j);
+    const bool elem = u.type == PDHCG_CONE_FREE || u.type == PDHCG_CONE_NONNEG;
+    if (elem && !cones.empty() && cones.back().type == u.type && cones.back().start + cones.back().dim == ns)
+      cones.back().dim += 1;
+    else
+      cones.push_back(ConeBlock{u.type, ns, u.dim, u.alpha});
+  }
+  std::vector<int> inv(n);
+  for (int j = 0; j < n; ++j) inv[perm[j]] = j;
+  // A: renumber columns, keep rows sorted by column
+  {
+    Csr& A = H.A;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t l = 0; l < A.rows; ++l) {
+      row.clear();
+      for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) row.emplace_back(inv[A.col[k]], A.val[k]);
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                  return a.first < b.first;
+                });
+      int64_t k = A.ptr[l];
+      for (const auto& e : row) {
+        A.col[k] = e.first;
+        A.val[k++] = e.second;
+      }
+    }
+  }
+  // P: rows and columns
+  if (H.P.rows > 0) {
+    Csr Q;
+    Q.rows = Q.cols = n;
+    Q.ptr.assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) Q.ptr[j + 1] = Q.ptr[j] + (H.P.ptr[perm[j] + 1] - H.P.ptr[perm[j]]);
+    Q.col.resize(H.P.nnz());
+    Q.val.resize(H.P.nnz());
+    std::vector<std::pair<int32_t, double>> row;
+    for (int j = 0; j < n; ++j) {
+      row.clear();
+      const int i = perm[j];
+      for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) row.emplace_back(inv[H.P.col[k]], H.P.val[k]);
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                  return a.first < b.first;
+                });
+      int64_t k = Q.ptr[j];
+      for (const auto& e : row) {
+        Q.col[k] = e.first;
+        Q.val[k++] = e.second;
+      }
+    }
+    H.P = std::move(Q);
+  }
+  // R columns, c, S_x
+  if (H.r > 0) {
+    std::vector<double> R2(H.R.size());
+    for (int a = 0; a < H.r; ++a)
+      for (int j = 0; j < n; ++j) R2[(size_t)a * n + j] = H.R[(size_t)a * n + perm[j]];
+    H.R.swap(R2);
+  }
+  std::vector<double> c2(n), s2(n);
+  for (int j = 0; j < n; ++j) {
+    c2[j] = H.c[perm[j]];
+    s2[j] = H.Sx[perm[j]];
+  }
+  H.c.swap(c2);
+  H.Sx.swap(s2);
+  H.cones.swap(cones);
+  H.perm.swap(perm);
 }
 
 // divide entry (l, i) by row[l] * col[i]
@@ -245,6 +353,9 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   const double qs = H.nu_b / H.nu_c;
   for (auto& v : H.P.val) v *= qs;
   for (auto& v : H.D) v *= qs;
+
+  // ---- device coordinate order ----------------------------------------------
+  if (s.interleave) interleave(H);
 
   // ---- transpose, diagonal of Q^, structure flags -------------------------
   H.AT = transpose(A);

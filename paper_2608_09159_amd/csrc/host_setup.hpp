@@ -34,6 +34,11 @@ struct HostInstance {
   bool p_diag = false;            // P present and diagonal: P u = pdiag * u
   std::vector<double> pdiag;      // diag(P^) when p_diag
   std::vector<ConeBlock> cones;
+  // device coordinate order: perm[j] = the caller's index of internal
+  // coordinate j (empty: the caller's order).  Cone blocks are interleaved
+  // with the elementwise coordinates so that contiguous ownership ranges
+  // mix both kinds of work.
+  std::vector<int> perm;
   // per-coordinate kind and cone work items
   std::vector<uint8_t> ctype;
   std::vector<int> wave_start, wave_dim;

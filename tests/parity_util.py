@@ -28,7 +28,7 @@ def oracle_settings(**kw):
 
 
 def trace_parity(prob, iters=50, check_every=4, x0=None, y0=None, **kw):
-    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a")}
+    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a", "interleave")}
     print(f"[parity] {prob.name} n={prob.n} m={prob.m} iters={iters} {kw}", flush=True)
     h = G.setup(prob, trace_iters=iters, check_every=check_every, max_iter=iters, **kw)
     try:
@@ -65,7 +65,7 @@ def assert_trace_matches(name, tr, o):
 def final_parity(prob, **kw):
     print(f"[final] {prob.name} n={prob.n} m={prob.m} {kw}", flush=True)
     g = G.solve(prob, **kw)
-    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a")}
+    okw = {k: v for k, v in kw.items() if k not in ("grid_dim", "lanes_at", "lanes_a", "interleave")}
     o = pdhg.solve(prob, oracle_settings(**okw))
     assert_final_matches(g, o)
     return g, o

@@ -83,6 +83,25 @@ def test_iterate_parity_options(opt):
     trace_parity(synth.mixed_cone_scaled(seed=2, scale=0.006), check_every=ce, **o)
 
 
+def test_iterate_parity_interleaved_order():
+    """interleave = 1 renumbers the coordinates on the device (cone blocks
+    spread among the R+ coordinates); iterates, traces and warm starts are
+    still in the caller's order."""
+    p = synth.mixed_cone_scaled(seed=5, scale=0.01)
+    trace_parity(p, interleave=1, grid_dim=4)
+    rng = np.random.default_rng(1)
+    q = synth.tiny_mixed(3)
+    trace_parity(q, interleave=1, x0=rng.standard_normal(q.n), y0=rng.standard_normal(q.m))
+
+
+def test_dual_slack_output_interleaved():
+    p = synth.tiny_mixed(0)
+    g = G.solve(p, want_s=True, interleave=1)
+    Q = p.P.toarray() + p.R.T @ p.D @ p.R
+    s = Q @ g["x"] + p.c - p.A.T @ g["y"]
+    np.testing.assert_allclose(g["s"], s, rtol=1e-9, atol=1e-12)
+
+
 def test_iterate_parity_warm_start():
     p = synth.tiny_mixed(0)
     rng = np.random.default_rng(0)
