@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 # HBM traffic of one solve_kernel launch on the default workload, from two
 # rocprofv3 counter runs (FETCH_SIZE x 1.99978, WRITE_SIZE x 1.0: the factors
@@ -33,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources whose hash is recorded, at the recorded grid; otherwise the
 # bench reports null.
 MEASURED_TRAFFIC = {
-    "workload": "mixed_cone", "grid": 196, "iterations": 448,
-    "sources_sha256": "152f98099fcc80254a7ce6474e5eb03bab5305ef3069842a2aefef0f87e8d800",
-    "bytes_per_launch": 14258337.4375 * 1024 * 1.99978 + 16720173.3125 * 1024 * 1.0,
+    "workload": "mixed_cone", "grid": 256, "iterations": 448,
+    "sources_sha256": "6023a6e9230d0ce382d3987f33661f2af01820831b5ebb54f43c2d52333562c2",
+    "bytes_per_launch": 11333469.3125 * 1024 * 1.99977 + 15795248.53125 * 1024 * 1.0,
 }
-KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp")
+KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
 
 def kernel_sources_hash():
@@ -244,6 +245,42 @@ def bench_warm(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mlp(args):
+    """Training steps of the full-size warm-start network (51,000 -> 512 ->
+    512 -> 56,500, batch 256) on synthetic data: the BF16 matrix-core GEMMs,
+    epilogues and Adam.  FLOPs counted: 6 x batch x sum of layer products
+    (forward, and the two backward products)."""
+    import torch
+    import paper_2608_09159_amd as pkg
+    dims, B = [51000, 512, 512, 56500], 256
+    rng = np.random.default_rng(0)
+    net = pkg.MLP(dims, B)
+    for l, (a, b) in enumerate(zip(dims[:-1], dims[1:])):
+        net.set_params(l, (rng.standard_normal((a, b)) * np.sqrt(2.0 / a)).astype(np.float32),
+                       np.zeros(b, np.float32))
+    X = torch.randn(B, dims[0], device="cuda")
+    Y = torch.randn(B, dims[-1], device="cuda")
+    for _ in range(args.warmup):
+        net.train_step(X, Y, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(X, Y, lr=1e-4)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    net.free()
+    flops = 6.0 * B * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+    tf = flops * args.steps / wall / 1e12
+    out = {"metric": "warm-start network training throughput", "value": tf, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+           "data": "synthetic", "config": {"workload": "warm-start network 51000-512-512-56500, batch 256"},
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / BF16_DENSE_PEAK_TFLOPS, "traffic": None,
+                        "note": "whole train step (GEMMs, split-K reductions, epilogues, Adam) per wall time"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +288,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixed_cone")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="cap on outer iterations per solve (0: none; for fixed-length profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-bulk and batched comparisons of the default line")
@@ -280,6 +319,9 @@ def main():
     if args.workload == "fisher_warm":
         bench_warm(args)
         return
+    if args.workload == "mlp_train":
+        bench_mlp(args)
+        return
     prob, wname = workload(args.workload)
     if args.workload == "portfolio_batch":
         print(json.dumps(bench_batch(args, prob, wname)), flush=True)
@@ -291,7 +333,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()
-    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream)
+    extra = {"max_iter": args.max_iter} if args.max_iter > 0 else {}
+    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream, **extra)
     res = None
     for _ in range(args.warmup):
         res = h.solve()
