@@ -26,8 +26,11 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
-constexpr int GT = 256;   // threads per GEMM workgroup
+constexpr int TM = 128, TN = 128, TK = 32, LDK = TK + 8;
+constexpr int GT = 256;   // threads per GEMM workgroup (4 waves, 2 x 2 of 64 x 64)
+constexpr int VW = 4;     // elements per vector load (8 bytes)
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
   const __bf16* A;
@@ -36,6 +39,7 @@ struct GemmArgs {
   int M, N, K;
   int kchunk;             // K range of one split (multiple of TK)
   int epi;
+  int vec_a, vec_b;       // leading dimension a multiple of VW: vector loads
   const float* bias;      // EPI_BIAS_*
   const __bf16* mask;     // EPI_MASK_BF16: M x N, ld = N
   float* outf;            // FP32 output (ld = N) or partials [splits][M][N]
@@ -54,70 +58,102 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float 
   }
 }
 
+// VW consecutive elements src[0..VW) along the contiguous dimension, zero
+// past `lim` (elements from the start of the run) or outside the tile
+__device__ __forceinline__ bf16x4 load_run(const __bf16* src, int lim, bool vec) {
+  bf16x4 v;
+  if (vec && lim >= VW) {
+    v = *reinterpret_cast<const bf16x4*>(src);
+  } else {
+    const __bf16 z = (__bf16)0.0f;
+#pragma unroll
+    for (int j = 0; j < VW; ++j) v[j] = j < lim ? src[j] : z;
+  }
+  return v;
+}
+
+// stage one operand tile of R rows (m or n) x TK (k) into S[row][k]:
+// k-contiguous storage (element (r, k) at P[r * ld + k]) or r-contiguous
+// storage (element (r, k) at P[k * ld + r])
+template <bool KCONTIG>
+__device__ __forceinline__ void stage(__bf16 (*S)[LDK], const __bf16* P, long ld, int r0, int rmax, int k0,
+                                      int kend, bool vec) {
+  const int tid = threadIdx.x;
+  const __bf16 zero = (__bf16)0.0f;
+  if (KCONTIG) {
+    // 128 rows x 8 runs of 4 k
+#pragma unroll
+    for (int q = 0; q < (TM * TK / VW) / GT; ++q) {
+      const int v = tid + q * GT;
+      const int r = v >> 3, kq = (v & 7) * VW;
+      const int row = r0 + r, k = k0 + kq;
+      bf16x4 x;
+      if (row < rmax && k < kend) x = load_run(P + (size_t)row * ld + k, kend - k, vec);
+      else x = bf16x4{zero, zero, zero, zero};
+      *reinterpret_cast<bf16x4*>(&S[r][kq]) = x;
+    }
+  } else {
+    // 32 k x 32 runs of 4 rows
+#pragma unroll
+    for (int q = 0; q < (TM * TK / VW) / GT; ++q) {
+      const int v = tid + q * GT;
+      const int kk = v >> 5, rq = (v & 31) * VW;
+      const int row = r0 + rq, k = k0 + kk;
+      bf16x4 x;
+      if (row < rmax && k < kend) x = load_run(P + (size_t)k * ld + row, rmax - row, vec);
+      else x = bf16x4{zero, zero, zero, zero};
+#pragma unroll
+      for (int j = 0; j < VW; ++j) S[rq + j][kk] = x[j];
+    }
+  }
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(GT) void gemm_kernel(GemmArgs g) {
-  __shared__ __bf16 As[TM][LDK];
-  __shared__ __bf16 Bs[TN][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = blockIdx.z * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  f32x16 acc = {};
-  const __bf16 zero = (__bf16)0.0f;
+  const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+  f32x16 acc[2][2] = {};
   for (int k0 = kb; k0 < ke; k0 += TK) {
-    // ---- stage A tile (TM x TK) as As[m][k]
-    if (!TA) {
-      const int r = tid >> 2, kq = (tid & 3) * 8;
-      const int m = m0 + r;
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kq + j;
-        As[r][kq + j] = (m < g.M && k < ke) ? g.A[(size_t)m * g.lda + k] : zero;
-      }
-    } else {
-      const int kk = tid >> 3, mq = (tid & 7) * 8;
-      const int k = k0 + kk;
-      for (int j = 0; j < 8; ++j) {
-        const int m = m0 + mq + j;
-        As[mq + j][kk] = (m < g.M && k < ke) ? g.A[(size_t)k * g.lda + m] : zero;
-      }
-    }
-    // ---- stage B tile (TK x TN) as Bs[n][k]
-    if (!TB) {
-      const int kk = tid >> 3, nq = (tid & 7) * 8;
-      const int k = k0 + kk;
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + nq + j;
-        Bs[nq + j][kk] = (n < g.N && k < ke) ? g.B[(size_t)k * g.ldb + n] : zero;
-      }
-    } else {
-      const int r = tid >> 2, kq = (tid & 3) * 8;
-      const int n = n0 + r;
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kq + j;
-        Bs[r][kq + j] = (n < g.N && k < ke) ? g.B[(size_t)n * g.ldb + k] : zero;
-      }
-    }
+    stage<!TA>(As, g.A, g.lda, m0, g.M, k0, ke, g.vec_a != 0);
+    stage<TB>(Bs, g.B, g.ldb, n0, g.N, k0, ke, g.vec_b != 0);
     __syncthreads();
-    // ---- two 32x32x16 steps; lane l holds row/col (l % 32), k (l / 32) * 8 + j
+    // lane l holds row/col (l % 32), k (l / 32) * 8 + j of each 32 x 32 x 16 step
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + (lane & 31)][ks + (lane >> 5) * 8]);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + (lane & 31)][ks + (lane >> 5) * 8]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + (lane & 31)][ks + (lane >> 5) * 8]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * i + (lane & 31)][ks + (lane >> 5) * 8]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  // ---- output: acc[j] is row (j / 4) * 8 + (l / 32) * 4 + j % 4, column l % 32
-  const int n = n0 + wn + (lane & 31);
+  // ---- output: acc[i][j][e] is row (e / 4) * 8 + (l / 32) * 4 + e % 4 of block
+  // i, column l % 32 of block j
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int m = m0 + wm + (j >> 2) * 8 + (lane >> 5) * 4 + (j & 3);
-    if (m < g.M && n < g.N) {
-      if (g.partial) g.outf[((size_t)blockIdx.z * g.M + m) * g.N + n] = acc[j];
-      else epilogue(g, m, n, acc[j]);
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + 32 * j + (lane & 31);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int m = m0 + wm + 32 * i + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+        if (m < g.M && n < g.N) {
+          if (g.partial) g.outf[((size_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][e];
+          else epilogue(g, m, n, acc[i][j][e]);
+        }
+      }
     }
-  }
 }
 
 // sum the split-K partials in split order, then the epilogue
@@ -151,19 +187,27 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(const float* yhat, const 
 }
 
 __global__ __launch_bounds__(64) void sum_partials_kernel(const double* part, int np, double* out) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < np; ++i) s += part[i];
-    out[0] = s;
-  }
+  // lane-strided sums, then a fixed-order wave reduction (deterministic)
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 64) s += part[i];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
-// db[n] = sum over rows of dz[b][n] (FP32, rows in order)
+// db[n] = sum over rows of dz[b][n] (FP32, rows in order; 8 loads in flight)
 __global__ __launch_bounds__(256) void colsum_kernel(const __bf16* dz, int rows, int N, float* db) {
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   float s = 0.0f;
-  for (int b = 0; b < rows; ++b) s += (float)dz[(size_t)b * N + n];
+  int b = 0;
+  for (; b + 8 <= rows; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (float)dz[(size_t)(b + j) * N + n];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; b < rows; ++b) s += (float)dz[(size_t)b * N + n];
   db[n] = s;
 }
 
@@ -201,6 +245,8 @@ hipError_t mlp_gemm(const __bf16* A, bool ta, long lda, const __bf16* B, bool tb
   g.N = N;
   g.K = K;
   g.epi = epi;
+  g.vec_a = (lda % VW == 0) ? 1 : 0;
+  g.vec_b = (ldb % VW == 0) ? 1 : 0;
   g.bias = bias;
   g.mask = mask;
   g.outf = outf;
