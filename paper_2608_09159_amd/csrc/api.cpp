@@ -60,6 +60,8 @@ struct Instance {
   double qmax = 0.0;
   int grid = 1;
   int lds_bytes = 0;           // dynamic LDS per workgroup for its slice of R
+  int* at_cls_perm = nullptr;  // all A^T rows by length class (skewed rows; setup products)
+  long at_cls_seg[6] = {0, 0, 0, 0, 0, 0};
   size_t bar_bytes = 0;
   long n_warm = 0;
 };
@@ -491,6 +493,22 @@ int upload_instance(Handle* h, Instance* I) {
         P.at_seg = B.upload(seg);
       }
     }
+    // the same length classes over all of A^T for the setup products
+    if (P.at_perm) {
+      std::vector<std::vector<int>> cls(5);
+      for (long i = 0; i < n; ++i) {
+        const long z = H.AT.ptr[i + 1] - H.AT.ptr[i];
+        cls[z <= 16 ? 0 : (z <= 64 ? 1 : (z <= 256 ? 2 : (z <= 1024 ? 3 : 4)))].push_back((int)i);
+      }
+      std::vector<int> all;
+      all.reserve(n);
+      for (int c = 0; c < 5; ++c) {
+        I->at_cls_seg[c] = (long)all.size();
+        all.insert(all.end(), cls[c].begin(), cls[c].end());
+      }
+      I->at_cls_seg[5] = (long)all.size();
+      I->at_cls_perm = B.upload(all);
+    }
     P.part_c = B.upload(pc);
     P.part_r = B.upload(pr);
     P.part_w = B.upload(pw);
@@ -519,7 +537,10 @@ int power_norm(Handle* h, Instance* I, double* out) {
   if (m == 0 || I->H.A.nnz() == 0) { *out = 0.0; return PDHCG_OK; }
   for (int it = 0; it < h->s.power_iters; ++it) {
     HIPCHK(launch_spmv(P.A_ptr, P.A_col, P.A_val, z, t, m, P.a_lanes, st));
-    HIPCHK(launch_spmv(P.AT_ptr, P.AT_col, P.AT_val, t, w, n, P.at_lanes, st));
+    if (I->at_cls_perm)
+      HIPCHK(launch_spmv_classes(P.AT_ptr, P.AT_col, P.AT_val, t, w, I->at_cls_perm, I->at_cls_seg, st));
+    else
+      HIPCHK(launch_spmv(P.AT_ptr, P.AT_col, P.AT_val, t, w, n, P.at_lanes, st));
     HIPCHK(launch_norm(w, n, part, nrm, st));
     HIPCHK(hipMemcpyAsync(z, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_scale(z, n, nrm, st));

@@ -1098,6 +1098,30 @@ __global__ __launch_bounds__(BLOCK) void spmv_kernel(const int64_t* ptr, const i
   }
 }
 
+// rows perm[0..count) with Lw lanes each (setup products of matrices with
+// skewed row lengths, one launch per length class)
+__global__ __launch_bounds__(BLOCK) void spmv_perm_kernel(const int64_t* ptr, const int* col,
+                                                         const double* val, const double* x, double* y,
+                                                         const int* perm, long count, int Lw) {
+  const int groups = BLOCK / Lw;
+  const int gid = threadIdx.x / Lw, sub = threadIdx.x & (Lw - 1);
+  for (long base = (long)blockIdx.x * groups; base < count; base += (long)gridDim.x * groups) {
+    const long q = base + gid;
+    const bool act = q < count;
+    const long row = act ? (long)perm[q] : 0;
+    const double s = spmv_row(ptr, col, val, x, row, sub, Lw, act);
+    if (act && sub == 0) y[row] = s;
+  }
+}
+
+// one workgroup per row of perm[0..count): the longest rows
+__global__ __launch_bounds__(BLOCK) void spmv_perm_block_kernel(const int64_t* ptr, const int* col,
+                                                               const double* val, const double* x,
+                                                               double* y, const int* perm, long count) {
+  for (long q = blockIdx.x; q < count; q += gridDim.x)
+    spmv_rows_block(ptr, col, val, x, y, (long)perm[q], (long)perm[q] + 1);
+}
+
 __global__ __launch_bounds__(BLOCK) void sumsq_partial_kernel(const double* x, long n, double* part) {
   __shared__ double red[NWAVE];
   double s = 0.0;
@@ -1297,6 +1321,26 @@ hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, co
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(spmv_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, ptr, col, val, x, y,
                      rows, Lw);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_classes(const int64_t* ptr, const int* col, const double* val, const double* x,
+                               double* y, const int* perm, const long* seg, hipStream_t st) {
+  static const int lanes[5] = {1, 4, 16, 64, BLOCK};
+  for (int c = 0; c < 5; ++c) {
+    const long cnt = seg[c + 1] - seg[c];
+    if (cnt <= 0) continue;
+    if (lanes[c] >= BLOCK) {
+      const long grid = std::min<long>(cnt, 4096);
+      hipLaunchKernelGGL(spmv_perm_block_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, ptr, col, val, x, y,
+                         perm + seg[c], cnt);
+    } else {
+      const long per = BLOCK / lanes[c];
+      const long grid = std::min<long>((cnt + per - 1) / per, 4096);
+      hipLaunchKernelGGL(spmv_perm_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, ptr, col, val, x, y,
+                         perm + seg[c], cnt, lanes[c]);
+    }
+  }
   return hipGetLastError();
 }
 

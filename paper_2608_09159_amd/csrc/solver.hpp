@@ -11,6 +11,9 @@ hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stre
 hipError_t max_coop_grid(int* out);
 hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, const double* x,
                        double* y, long rows, int Lw, hipStream_t st);
+// rows of perm in five length classes (seg[0..5]: class boundaries in perm)
+hipError_t launch_spmv_classes(const int64_t* ptr, const int* col, const double* val, const double* x,
+                               double* y, const int* perm, const long* seg, hipStream_t st);
 hipError_t launch_norm(const double* x, long n, double* part, double* nrm, hipStream_t st);
 hipError_t launch_scale(double* x, long n, const double* nrm, hipStream_t st);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t st);
