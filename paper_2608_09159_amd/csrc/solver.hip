@@ -46,7 +46,6 @@ constexpr int NWAVE = BLOCK / 64;
 struct Lds {
   double red[16][NWAVE];
   double scal[SL_COUNT];
-  double hw[NWAVE][RMAX];
   double ht[RMAX];       // D^ h for the Q product of the current pass
   double Dl[RMAX * RMAX];  // D^ (r x r), staged once per run
   double hu[RMAX];       // R^ u of the current inner iterate
@@ -168,11 +167,6 @@ __device__ void block_store(Lds& L, const double* v, const int* slots, int k, do
   __syncthreads();
 }
 
-__device__ __forceinline__ void hw_clear(Lds& L) {
-  for (int i = threadIdx.x; i < NWAVE * RMAX; i += BLOCK) (&L.hw[0][0])[i] = 0.0;
-  __syncthreads();
-}
-
 // the dense factor R (r x n, row-major) as read by one workgroup: from its
 // LDS copy of the owned columns [c0, c0 + nl) when there is one, else from
 // global memory.  Every R access of a solve is to an owned column, so a
@@ -189,16 +183,22 @@ struct RSrc {
   }
 };
 
-// wave-uniform: add R[k, i] * val (0 if !active) to the wave's accumulators
-// (the product in the factor's precision, the sums in FP64)
+// the workgroup's share of R v over its coordinates [c0, c1) into the
+// partial slots SL_H0 + k: wave w sums rows k = w, w + NWAVE, ... (products
+// in the factor's precision, sums in FP64); v was written by this workgroup
 template <class MV>
-__device__ __forceinline__ void hw_add(Lds& L, const RSrc<MV>& R, int r, long i, double val, bool active) {
+__device__ __forceinline__ void hw_reduce_store(Lds& L, const RSrc<MV>& R, int r, const double* v, long c0,
+                                                long c1, double* partials, int G, int rank) {
+  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = 0; k < r; ++k) {
-    double t = active ? (double)(R(k, i) * (MV)val) : 0.0;
-    t = wave_sum(t);
-    if (lane == 0) L.hw[wv][k] += t;
+  for (int k = wv; k < r; k += NWAVE) {
+    double s = 0.0;
+#pragma unroll 4
+    for (long i = c0 + lane; i < c1; i += 64) s += (double)(R(k, i) * (MV)v[i]);
+    s = wave_sum(s);
+    if (lane == 0) partials[(size_t)(SL_H0 + k) * G + rank] = s;
   }
+  __syncthreads();
 }
 
 // sum_k R[k, i] ht[k] in increasing k, accumulated in the factor's precision
@@ -207,16 +207,6 @@ __device__ __forceinline__ double r_dot(const RSrc<MV>& R, int r, long i, const 
   MV acc = 0;
   for (int k = 0; k < r; ++k) acc += R(k, i) * (MV)ht[k];
   return (double)acc;
-}
-
-__device__ void hw_store(Lds& L, int r, double* partials, int G, int rank) {
-  __syncthreads();
-  if ((int)threadIdx.x < r) {
-    double s = 0.0;
-    for (int w = 0; w < NWAVE; ++w) s += L.hw[w][threadIdx.x];
-    partials[(size_t)(SL_H0 + threadIdx.x) * G + rank] = s;
-  }
-  __syncthreads();
 }
 
 // reduce `k` slots over the G partials into L.scal[slot]
@@ -240,6 +230,37 @@ __device__ void team_reduce_h(Lds& L, const double* partials, int G, int r, doub
     for (int j = lane; j < G; j += 64) s += p[j];
     s = wave_sum(s);
     if (lane == 0) dst[k] = s;
+  }
+  __syncthreads();
+}
+
+// team_reduce of `k` slots and team_reduce_h of the r factor slots in one
+// pass (the loads of two slots per wave in flight together); the same
+// per-slot summation order as the two separate calls
+__device__ __forceinline__ void team_reduce_sh(Lds& L, const double* partials, int G, const int* slots, int k,
+                                               int r, double* dsth) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ns = k + r;
+  for (int i0 = wv; i0 < ns; i0 += 2 * NWAVE) {
+    const int i1 = i0 + NWAVE;
+    const bool two = i1 < ns;
+    const double* p0 = partials + (size_t)(i0 < k ? slots[i0] : SL_H0 + i0 - k) * G;
+    const double* p1 = partials + (size_t)(!two ? 0 : (i1 < k ? slots[i1] : SL_H0 + i1 - k)) * G;
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = lane; j < G; j += 64) {
+      s0 += p0[j];
+      if (two) s1 += p1[j];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      if (i0 < k) L.scal[slots[i0]] = s0;
+      else dsth[i0 - k] = s0;
+      if (two) {
+        if (i1 < k) L.scal[slots[i1]] = s1;
+        else dsth[i1 - k] = s1;
+      }
+    }
   }
   __syncthreads();
 }
@@ -566,22 +587,19 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   // ------------------------------------------------------------------ init
   if (!L.C.started) {
     // x = Pi_K(x0^) (zb holds the scaled warm start or zeros); a_x = x
-    hw_clear(L);
     for_range(c0, c1, [&](long i, bool act) {
       bool el = act && P.ctype[i] != CT_CONE;
       double x = el ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
       if (el) { V.x[i] = x; V.ax[i] = x; }
-      hw_add(L, R64, r, i, x, el);
     });
     if (has_items) {
       project_items(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
       for_item_coords(P, IT, [&](long i, bool act) {
         double x = act ? V.zb[i] : 0.0;
         if (act) { V.x[i] = x; V.ax[i] = x; }
-        hw_add(L, R64, r, i, x, act);
       });
     }
-    hw_store(L, r, part, G, rank);
+    hw_reduce_store(L, R64, r, V.x, c0, c1, part, G, rank);
     SYNC_OR_EXIT();
     for_rows_range(r0, r1, own.lr, [&](long row, int sub, bool act) {
       double ax = spmv_row(P.A_ptr, P.A_col, P.A_val, V.x, row, sub, own.lr, act);
@@ -657,7 +675,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       }
     } else {
       double d2 = 0.0;
-      hw_clear(L);
       for_range(c0, c1, [&](long i, bool act) {
         double un = 0.0;
         bool el = false;
@@ -680,7 +697,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.zb[i] = z;
           }
         }
-        hw_add(L, RB, r, i, un, el);
       });
       if (has_items) {
         __syncthreads();
@@ -693,12 +709,11 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             const double dd = un - V.up[i];
             d2 += dd * dd;
           }
-          hw_add(L, RB, r, i, un, act);
         });
       }
       const int sl[1] = {SL_DELTA2};
       block_store(L, &d2, sl, 1, part, G, rank);
-      hw_store(L, r, part, G, rank);
+      hw_reduce_store(L, RB, r, V.u, c0, c1, part, G, rank);
     }
     SYNC_OR_EXIT();
 
@@ -707,8 +722,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if (!P.q_diag) {
       {
         const int sl[1] = {SL_DELTA2};
-        team_reduce(L, part, G, sl, 1);
-        team_reduce_h(L, part, G, r, L.hu);
+        team_reduce_sh(L, part, G, sl, 1, r, L.hu);
       }
       jcount = 1;
       bool done = (S.fixed_inner <= 0) && (sqrt(L.scal[SL_DELTA2]) <= eps_in);
@@ -748,7 +762,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         // ---- P4: projected step
         tmark(L, prof, PT_P4);
         double d2 = 0.0;
-        hw_clear(L);
         for_range(c0, c1, [&](long i, bool act) {
           const bool el = act && P.ctype[i] != CT_CONE;
           double un = 0.0;
@@ -761,7 +774,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.gp[i] = gi;
             V.u[i] = un;
           }
-          hw_add(L, RB, r, i, un, el);
         });
         if (has_items) {
           PROJ(project_items(P, IT, !jac,
@@ -777,19 +789,17 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
               V.gp[i] = V.g[i];
               V.u[i] = un;
             }
-            hw_add(L, RB, r, i, un, act);
           });
         }
         {
           const int sl[1] = {SL_DELTA2};
           block_store(L, &d2, sl, 1, part, G, rank);
-          hw_store(L, r, part, G, rank);
+          hw_reduce_store(L, RB, r, V.u, c0, c1, part, G, rank);
         }
         SYNC_OR_EXIT();
         {
           const int sl[1] = {SL_DELTA2};
-          team_reduce(L, part, G, sl, 1);
-          team_reduce_h(L, part, G, r, L.hu);
+          team_reduce_sh(L, part, G, sl, 1, r, L.hu);
         }
         ++jcount;
         done = (S.fixed_inner <= 0) && (sqrt(L.scal[SL_DELTA2]) <= eps_in);
@@ -828,7 +838,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           }
         }
       });
-      if (!check) hw_clear(L);
       for_range(c0, c1, [&](long i, bool act) {
         double xn = 0.0;
         if (act) {
@@ -846,7 +855,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
-        if (!check) hw_add(L, RB, r, i, xn, act);
       });
       if (check) {
         const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
@@ -854,7 +862,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       } else {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &acc[5], sl, 1, part, G, rank);
-        hw_store(L, r, part, G, rank);
+        hw_reduce_store(L, RB, r, V.x, c0, c1, part, G, rank);
       }
     }
     SYNC_OR_EXIT();
@@ -868,8 +876,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if (!check) {
       {
         const int sl[1] = {SL_XMOV2};
-        team_reduce(L, part, G, sl, 1);
-        team_reduce_h(L, part, G, r, L.C.hx);
+        team_reduce_sh(L, part, G, sl, 1, r, L.C.hx);
       }
       if (tid == 0) {
         L.C.eps_in = fmin(L.C.eps_in, fmax(S.gamma_in * sqrt(L.scal[SL_XMOV2]) / tau, S.eps_min));
@@ -986,7 +993,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     tmark(L, prof, PT_HALP);
     {
       double xm = 0.0;
-      if (!restart) hw_clear(L);
       for (long l = r0 + tid; l < r1; l += BLOCK) {
         const double wy = V.wy[l], aw = V.Aw[l];
         if (restart) {
@@ -1009,12 +1015,11 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
-        if (!restart) hw_add(L, RB, r, i, xn, act);
       });
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &xm, sl, 1, part, G, rank);
-        hw_store(L, r, part, G, rank);
+        hw_reduce_store(L, RB, r, V.x, c0, c1, part, G, rank);
       }
     }
     SYNC_OR_EXIT();
@@ -1024,8 +1029,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     } else {
       {
         const int sl[1] = {SL_XMOV2};
-        team_reduce(L, part, G, sl, 1);
-        team_reduce_h(L, part, G, r, L.C.hx);
+        team_reduce_sh(L, part, G, sl, 1, r, L.C.hx);
       }
       if (tid == 0) {
         L.C.eps_in = fmin(L.C.eps_in, fmax(S.gamma_in * sqrt(L.scal[SL_XMOV2]) / tau, S.eps_min));
