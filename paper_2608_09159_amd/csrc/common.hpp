@@ -30,9 +30,10 @@ enum Slot : int {
   SL_MOVX2,        // ||w_x - a_x||^2                (PID)
   SL_MOVY2,        // ||w_y - a_y||^2
   SL_NAN,          // count of non-finite values
-  SL_QMAX,         // unused slot kept for alignment
+  SL_SPS,          // <s, P s>, diagonal P          (one-sync inner step)
   SL_H0,           // R u : RMAX slots
-  SL_COUNT = SL_H0 + RMAX
+  SL_HS0 = SL_H0 + RMAX,   // R s : RMAX slots (one-sync inner step)
+  SL_COUNT = SL_HS0 + RMAX
 };
 
 struct DevProblem {

@@ -49,6 +49,7 @@ struct Lds {
   double ht[RMAX];       // D^ h for the Q product of the current pass
   double Dl[RMAX * RMAX];  // D^ (r x r), staged once per run
   double hu[RMAX];       // R^ u of the current inner iterate
+  double hs[RMAX];       // R^ s, s = u - u_prev (one-sync inner step)
   Ctl C;
   int flag;
   int done;
@@ -151,7 +152,7 @@ struct SoloTeam {
 // workgroup reductions into per-workgroup partials
 // ---------------------------------------------------------------------------
 // sum of up to 16 per-thread values over the workgroup; partial[slot * G + rank]
-__device__ void block_store(Lds& L, const double* v, const int* slots, int k, double* partials,
+__device__ __forceinline__ void block_store(Lds& L, const double* v, const int* slots, int k, double* partials,
                             int G, int rank) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = 0; i < k; ++i) {
@@ -184,19 +185,36 @@ struct RSrc {
 };
 
 // the workgroup's share of R v over its coordinates [c0, c1) into the
-// partial slots SL_H0 + k: wave w sums rows k = w, w + NWAVE, ... (products
-// in the factor's precision, sums in FP64); v was written by this workgroup
+// partial slots SL_H0 + k, and with vp also R (v - vp) into SL_HS0 + k: one
+// wave per sum, up to three sums per wave at a time; products in the
+// factor's precision, sums in FP64.  v (and vp) were written by this
+// workgroup.
 template <class MV>
-__device__ __forceinline__ void hw_reduce_store(Lds& L, const RSrc<MV>& R, int r, const double* v, long c0,
-                                                long c1, double* partials, int G, int rank) {
+__device__ __forceinline__ void hw_reduce_store(Lds& L, const RSrc<MV>& R, int r, const double* v,
+                                                const double* vp, long c0, long c1, double* partials, int G,
+                                                int rank) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < r; k += NWAVE) {
-    double s = 0.0;
-#pragma unroll 4
-    for (long i = c0 + lane; i < c1; i += 64) s += (double)(R(k, i) * (MV)v[i]);
-    s = wave_sum(s);
-    if (lane == 0) partials[(size_t)(SL_H0 + k) * G + rank] = s;
+  const int nsum = vp ? 2 * r : r;
+  for (int q0 = wv; q0 < nsum; q0 += 3 * NWAVE) {
+    int kk[3];
+    bool dd[3], on[3];
+    for (int t = 0; t < 3; ++t) {
+      const int q = q0 + t * NWAVE;
+      on[t] = q < nsum;
+      dd[t] = on[t] && q >= r;
+      kk[t] = !on[t] ? 0 : (dd[t] ? q - r : q);
+    }
+    double s[3] = {0.0, 0.0, 0.0};
+    for (long i = c0 + lane; i < c1; i += 64) {
+      const double vi = v[i];
+      const double di = vp ? vi - vp[i] : 0.0;
+      for (int t = 0; t < 3; ++t) s[t] += (double)(R(kk[t], i) * (MV)(dd[t] ? di : vi));
+    }
+    for (int t = 0; t < 3; ++t) {
+      const double tot = wave_sum(s[t]);
+      if (lane == 0 && on[t]) partials[(size_t)((dd[t] ? SL_HS0 : SL_H0) + kk[t]) * G + rank] = tot;
+    }
   }
   __syncthreads();
 }
@@ -209,64 +227,83 @@ __device__ __forceinline__ double r_dot(const RSrc<MV>& R, int r, long i, const 
   return (double)acc;
 }
 
-// reduce `k` slots over the G partials into L.scal[slot]
-__device__ void team_reduce(Lds& L, const double* partials, int G, const int* slots, int k) {
+// sum over the G workgroup partials of `ns` slots: one wave per slot, up to
+// three slots per wave at a time with all their loads in flight together;
+// slot q is read from slot_of(q), its total written to *dst_of(q)
+template <class SlotFn, class DstFn>
+__device__ __forceinline__ void team_reduce_g(const double* partials, int G, int ns, SlotFn slot_of,
+                                              DstFn dst_of) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = wv; i < k; i += NWAVE) {
-    const double* p = partials + (size_t)slots[i] * G;
-    double s = 0.0;
-    for (int j = lane; j < G; j += 64) s += p[j];
-    s = wave_sum(s);
-    if (lane == 0) L.scal[slots[i]] = s;
-  }
-  __syncthreads();
-}
-
-__device__ void team_reduce_h(Lds& L, const double* partials, int G, int r, double* dst) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < r; k += NWAVE) {
-    const double* p = partials + (size_t)(SL_H0 + k) * G;
-    double s = 0.0;
-    for (int j = lane; j < G; j += 64) s += p[j];
-    s = wave_sum(s);
-    if (lane == 0) dst[k] = s;
-  }
-  __syncthreads();
-}
-
-// team_reduce of `k` slots and team_reduce_h of the r factor slots in one
-// pass (the loads of two slots per wave in flight together); the same
-// per-slot summation order as the two separate calls
-__device__ __forceinline__ void team_reduce_sh(Lds& L, const double* partials, int G, const int* slots, int k,
-                                               int r, double* dsth) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ns = k + r;
-  for (int i0 = wv; i0 < ns; i0 += 2 * NWAVE) {
-    const int i1 = i0 + NWAVE;
-    const bool two = i1 < ns;
-    const double* p0 = partials + (size_t)(i0 < k ? slots[i0] : SL_H0 + i0 - k) * G;
-    const double* p1 = partials + (size_t)(!two ? 0 : (i1 < k ? slots[i1] : SL_H0 + i1 - k)) * G;
-    double s0 = 0.0, s1 = 0.0;
+  for (int q0 = wv; q0 < ns; q0 += 3 * NWAVE) {
+    const int q1 = q0 + NWAVE, q2 = q0 + 2 * NWAVE;
+    const double* p0 = partials + (size_t)slot_of(q0) * G;
+    const double* p1 = q1 < ns ? partials + (size_t)slot_of(q1) * G : p0;
+    const double* p2 = q2 < ns ? partials + (size_t)slot_of(q2) * G : p0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int j = lane; j < G; j += 64) {
       s0 += p0[j];
-      if (two) s1 += p1[j];
+      s1 += p1[j];
+      s2 += p2[j];
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
     if (lane == 0) {
-      if (i0 < k) L.scal[slots[i0]] = s0;
-      else dsth[i0 - k] = s0;
-      if (two) {
-        if (i1 < k) L.scal[slots[i1]] = s1;
-        else dsth[i1 - k] = s1;
-      }
+      *dst_of(q0) = s0;
+      if (q1 < ns) *dst_of(q1) = s1;
+      if (q2 < ns) *dst_of(q2) = s2;
     }
+  }
+  __syncthreads();
+}
+
+// reduce `k` slots over the G partials into L.scal[slot]
+__device__ __forceinline__ void team_reduce(Lds& L, const double* partials, int G, const int* slots, int k) {
+  team_reduce_g(partials, G, k, [&](int q) { return slots[q]; }, [&](int q) { return &L.scal[slots[q]]; });
+}
+
+// the r factor slots into dst
+__device__ __forceinline__ void team_reduce_h(Lds& L, const double* partials, int G, int r, double* dst) {
+  team_reduce_g(partials, G, r, [&](int q) { return (int)SL_H0 + q; }, [&](int q) { return &dst[q]; });
+}
+
+// `k` scalar slots and the r factor slots in one round
+__device__ __forceinline__ void team_reduce_sh(Lds& L, const double* partials, int G, const int* slots, int k,
+                                               int r, double* dsth) {
+  team_reduce_g(partials, G, k + r, [&](int q) { return q < k ? slots[q] : (int)SL_H0 + q - k; },
+                [&](int q) { return q < k ? &L.scal[slots[q]] : &dsth[q - k]; });
+}
+
+// after a projected step of the one-sync inner loop: ||s||^2, <s, M s>,
+// <s, P s> into L.scal, R u into L.hu, R s into L.hs (one round), then the
+// BB denominator <s, P s> + (R s)^T D (R s) + ||s||^2 / tau into
+// L.scal[SL_SDG]
+__device__ __forceinline__ void team_reduce_s(Lds& L, const double* partials, int G, int r, double tau) {
+  team_reduce_g(partials, G, 3 + 2 * r,
+                [&](int q) {
+                  return q == 0 ? (int)SL_DELTA2 : q == 1 ? (int)SL_SJS : q == 2 ? (int)SL_SPS
+                       : q < 3 + r ? (int)SL_H0 + (q - 3) : (int)SL_HS0 + (q - 3 - r);
+                },
+                [&](int q) -> double* {
+                  return q == 0 ? &L.scal[SL_DELTA2] : q == 1 ? &L.scal[SL_SJS] : q == 2 ? &L.scal[SL_SPS]
+                       : q < 3 + r ? &L.hu[q - 3] : &L.hs[q - 3 - r];
+                });
+  if (threadIdx.x < 64) {
+    const int a = threadIdx.x;
+    double t = 0.0;
+    if (a < r) {
+      double u = 0.0;
+      for (int b = 0; b < r; ++b) u += L.Dl[a * r + b] * L.hs[b];
+      t = L.hs[a] * u;
+    }
+    t = wave_sum(t);
+    if (a == 0) L.scal[SL_SDG] = L.scal[SL_SPS] + t + L.scal[SL_DELTA2] / tau;
   }
   __syncthreads();
 }
 
 // L.ht = D h
-__device__ void make_ht(Lds& L, const DevProblem& P, const double* h) {
+__device__ __forceinline__ void make_ht(Lds& L, const DevProblem& P, const double* h) {
   __syncthreads();
   if ((int)threadIdx.x < P.r) {
     double s = 0.0;
@@ -318,7 +355,7 @@ __device__ __noinline__ void spmv_rows_block(const int64_t* ptr, const int* col,
 }
 
 template <class MV>
-__device__ void spmv_range(const int64_t* ptr, const int* col, const MV* val, const double* x,
+__device__ __forceinline__ void spmv_range(const int64_t* ptr, const int* col, const MV* val, const double* x,
                            double* out, long r0, long r1, int Lw) {
   if (Lw >= BLOCK) {
     spmv_rows_block(ptr, col, val, x, out, r0, r1);
@@ -452,7 +489,7 @@ struct Items {
 // item (wave items first, then lane items), read as starting points and
 // overwritten with the new roots
 template <class MakeSrc>
-__device__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
+__device__ __forceinline__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
                               double* dst, double* warm, unsigned long long* ptw = nullptr) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;                       // groups per wave
@@ -492,7 +529,7 @@ __device__ void project_items(const DevProblem& P, const Items& I, bool force_eu
 // wave-uniform iteration over the coordinates of this workgroup's cone items
 // (same item-to-group mapping as project_items)
 template <class F>
-__device__ void for_item_coords(const DevProblem& P, const Items& I, F f) {
+__device__ __forceinline__ void for_item_coords(const DevProblem& P, const Items& I, F f) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;
   const int gl = lane & (I.lg - 1);
@@ -599,7 +636,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         if (act) { V.x[i] = x; V.ax[i] = x; }
       });
     }
-    hw_reduce_store(L, R64, r, V.x, c0, c1, part, G, rank);
+    hw_reduce_store(L, R64, r, V.x, nullptr, c0, c1, part, G, rank);
     SYNC_OR_EXIT();
     for_rows_range(r0, r1, own.lr, [&](long row, int sub, bool act) {
       double ax = spmv_row(P.A_ptr, P.A_col, P.A_val, V.x, row, sub, own.lr, act);
@@ -628,6 +665,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   }
 
   const bool jac = S.inner == PDHCG_INNER_JACOBI;
+  // P diagonal or absent: one grid synchronisation per inner step (a sparse
+  // P needs the neighbours' s for <s, P s>: two)
+  const bool fuse = !P.q_diag && (P.p_diag || !P.P_ptr);
   const double rho = S.rho;
   const int La = own.la, Lr = own.lr;
 
@@ -674,25 +714,30 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         PROJ(project_items(P, IT, false, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.wx, V.warm));
       }
     } else {
-      double d2 = 0.0;
+      // acc: ||s||^2, <s, M s>, <s, P s> of the first step s = u - x (the
+      // last two for the one-sync inner step only)
+      double acc[3] = {0.0, 0.0, 0.0};
       for_range(c0, c1, [&](long i, bool act) {
-        double un = 0.0;
-        bool el = false;
         if (act) {
           const double xi = V.x[i];
           const double vi = xi + tau * V.t1[i];
           const double ru = r_dot(RB, r, i, L.ht);
           const double pu = P.p_diag ? P.Pd[i] * xi : (P.P_ptr ? V.t2[i] : 0.0);
           const double g0 = pu + ru + P.c[i] + (xi - vi) / tau;
-          const double z = xi - alpha0 * g0 / Mq(i);
+          const double mi = Mq(i);
+          const double z = xi - alpha0 * g0 / mi;
           V.v[i] = vi;
-          V.gp[i] = g0;
+          if (!fuse) V.gp[i] = g0;
           V.up[i] = xi;
           if (P.ctype[i] != CT_CONE) {
-            el = true;
-            un = elem_proj(P.ctype[i], z);
+            const double un = elem_proj(P.ctype[i], z);
             V.u[i] = un;
-            d2 += (un - xi) * (un - xi);
+            const double si = un - xi;
+            acc[0] += si * si;
+            if (fuse) {
+              acc[1] += si * (mi * si);
+              if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+            }
           } else {
             V.zb[i] = z;
           }
@@ -702,25 +747,39 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         __syncthreads();
         PROJ(project_items(P, IT, !jac, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb, V.warm));
         for_item_coords(P, IT, [&](long i, bool act) {
-          double un = 0.0;
           if (act) {
-            un = V.zb[i];
+            const double un = V.zb[i];
             V.u[i] = un;
-            const double dd = un - V.up[i];
-            d2 += dd * dd;
+            const double si = un - V.up[i];
+            acc[0] += si * si;
+            if (fuse) {
+              acc[1] += si * (Mq(i) * si);
+              if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+            }
           }
         });
       }
-      const int sl[1] = {SL_DELTA2};
-      block_store(L, &d2, sl, 1, part, G, rank);
-      hw_reduce_store(L, RB, r, V.u, c0, c1, part, G, rank);
+      const int sl[3] = {SL_DELTA2, SL_SJS, SL_SPS};
+      block_store(L, acc, sl, fuse ? 3 : 1, part, G, rank);
+      if (fuse) hw_reduce_store(L, RB, r, V.u, V.up, c0, c1, part, G, rank);
+      else hw_reduce_store(L, RB, r, V.u, nullptr, c0, c1, part, G, rank);
     }
     SYNC_OR_EXIT();
 
     // -------------------------------------------------------------- inner loop
     int jcount = 0;
     if (!P.q_diag) {
-      {
+      // With P diagonal or absent (fuse) an inner step takes one grid
+      // synchronisation: the prox gradient g(u) = P u + R^T D R u + c +
+      // (u - v) / tau is affine in u, so the BB denominator
+      // <s, g(u) - g(u_prev)> equals <s, P s> + (R s)^T D (R s) + ||s||^2 / tau
+      // with s = u - u_prev; each projected step accumulates these sums and
+      // R s beside ||s||^2 and R u, and the one reduction after it gives the
+      // next step size.  Otherwise the gradient pass reduces the BB sums
+      // before the step (two synchronisations).
+      if (fuse) {
+        team_reduce_s(L, part, G, r, tau);
+      } else {
         const int sl[1] = {SL_DELTA2};
         team_reduce_sh(L, part, G, sl, 1, r, L.hu);
       }
@@ -728,76 +787,109 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       bool done = (S.fixed_inner <= 0) && (sqrt(L.scal[SL_DELTA2]) <= eps_in);
       const int jmax = S.fixed_inner > 0 ? S.fixed_inner : S.j_max;
       while (!done && jcount < jmax) {
-        // ---- P3: gradient at u, BB reductions
+        double alpha;
         tmark(L, prof, PT_P3);
-        if (P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, M.Pv, V.u, V.t2, c0, c1, La);
-        make_ht(L, P, L.hu);
+        if (fuse) {
+          const double den = L.scal[SL_SDG];
+          const double num = jac ? L.scal[SL_SJS] : L.scal[SL_DELTA2];
+          alpha = den > 0.0 ? num / den : 1.0;
+          make_ht(L, P, L.hu);
+        } else {
+          // ---- P3: gradient at u, BB reductions
+          if (P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, M.Pv, V.u, V.t2, c0, c1, La);
+          make_ht(L, P, L.hu);
+          double acc[3] = {0.0, 0.0, 0.0};
+          for_range(c0, c1, [&](long i, bool act) {
+            if (!act) return;
+            const double ru = r_dot(RB, r, i, L.ht);
+            const double ui = V.u[i];
+            const double pu = P.p_diag ? P.Pd[i] * ui : (P.P_ptr ? V.t2[i] : 0.0);
+            const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
+            const double si = ui - V.up[i];
+            const double dg = gc - V.gp[i];
+            const double di = Mq(i);
+            acc[0] += si * (di * si);
+            acc[1] += si * dg;
+            acc[2] += si * si;
+            V.g[i] = gc;
+          });
+          {
+            const int sl[3] = {SL_SJS, SL_SDG, SL_SS};
+            block_store(L, acc, sl, 3, part, G, rank);
+          }
+          SYNC_OR_EXIT();
+          {
+            const int sl[3] = {SL_SJS, SL_SDG, SL_SS};
+            team_reduce(L, part, G, sl, 3);
+          }
+          const double den = L.scal[SL_SDG];
+          const double num = jac ? L.scal[SL_SJS] : L.scal[SL_SS];
+          alpha = den > 0.0 ? num / den : 1.0;
+        }
+        // ---- P4: projected step (fuse: the gradient is formed here)
+        tmark(L, prof, PT_P4);
         double acc[3] = {0.0, 0.0, 0.0};
         for_range(c0, c1, [&](long i, bool act) {
           if (!act) return;
-          const double ru = r_dot(RB, r, i, L.ht);
+          const bool el = P.ctype[i] != CT_CONE;
           const double ui = V.u[i];
-          const double pu = P.p_diag ? P.Pd[i] * ui : (P.P_ptr ? V.t2[i] : 0.0);
-          const double gc = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
-          const double si = ui - V.up[i];
-          const double dg = gc - V.gp[i];
-          const double di = Mq(i);
-          acc[0] += si * (di * si);
-          acc[1] += si * dg;
-          acc[2] += si * si;
-          V.g[i] = gc;
-        });
-        {
-          const int sl[3] = {SL_SJS, SL_SDG, SL_SS};
-          block_store(L, acc, sl, 3, part, G, rank);
-        }
-        SYNC_OR_EXIT();
-        {
-          const int sl[3] = {SL_SJS, SL_SDG, SL_SS};
-          team_reduce(L, part, G, sl, 3);
-        }
-        const double den = L.scal[SL_SDG];
-        const double num = jac ? L.scal[SL_SJS] : L.scal[SL_SS];
-        const double alpha = den > 0.0 ? num / den : 1.0;
-        // ---- P4: projected step
-        tmark(L, prof, PT_P4);
-        double d2 = 0.0;
-        for_range(c0, c1, [&](long i, bool act) {
-          const bool el = act && P.ctype[i] != CT_CONE;
-          double un = 0.0;
+          double gi;
+          if (fuse) {
+            const double ru = r_dot(RB, r, i, L.ht);
+            const double pu = P.p_diag ? P.Pd[i] * ui : 0.0;
+            gi = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
+            if (!el) V.g[i] = gi;
+          } else {
+            if (!el) return;
+            gi = V.g[i];
+          }
           if (el) {
-            const double ui = V.u[i];
-            const double gi = V.g[i];
-            un = elem_proj(P.ctype[i], ui - alpha * gi / Mq(i));
-            d2 += (un - ui) * (un - ui);
+            const double mi = Mq(i);
+            const double un = elem_proj(P.ctype[i], ui - alpha * gi / mi);
+            const double si = un - ui;
+            acc[0] += si * si;
+            if (fuse) {
+              acc[1] += si * (mi * si);
+              if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+            } else {
+              V.gp[i] = gi;
+            }
             V.up[i] = ui;
-            V.gp[i] = gi;
             V.u[i] = un;
           }
         });
         if (has_items) {
+          if (fuse) __syncthreads();
           PROJ(project_items(P, IT, !jac,
                              [&](long st) { return StepSrc{V.u, V.g, Mq, alpha, st}; }, V.zb, V.warm,
                              prof ? &L.pt[PT_WCALL] : nullptr));
           for_item_coords(P, IT, [&](long i, bool act) {
-            double un = 0.0;
             if (act) {
-              un = V.zb[i];
+              const double un = V.zb[i];
               const double ui = V.u[i];
-              d2 += (un - ui) * (un - ui);
+              const double si = un - ui;
+              acc[0] += si * si;
+              if (fuse) {
+                acc[1] += si * (Mq(i) * si);
+                if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+              } else {
+                V.gp[i] = V.g[i];
+              }
               V.up[i] = ui;
-              V.gp[i] = V.g[i];
               V.u[i] = un;
             }
           });
         }
         {
-          const int sl[1] = {SL_DELTA2};
-          block_store(L, &d2, sl, 1, part, G, rank);
-          hw_reduce_store(L, RB, r, V.u, c0, c1, part, G, rank);
+          const int sl[3] = {SL_DELTA2, SL_SJS, SL_SPS};
+          block_store(L, acc, sl, fuse ? 3 : 1, part, G, rank);
+          if (fuse) hw_reduce_store(L, RB, r, V.u, V.up, c0, c1, part, G, rank);
+          else hw_reduce_store(L, RB, r, V.u, nullptr, c0, c1, part, G, rank);
         }
         SYNC_OR_EXIT();
-        {
+        if (fuse) {
+          team_reduce_s(L, part, G, r, tau);
+        } else {
           const int sl[1] = {SL_DELTA2};
           team_reduce_sh(L, part, G, sl, 1, r, L.hu);
         }
@@ -862,7 +954,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       } else {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &acc[5], sl, 1, part, G, rank);
-        hw_reduce_store(L, RB, r, V.x, c0, c1, part, G, rank);
+        hw_reduce_store(L, RB, r, V.x, nullptr, c0, c1, part, G, rank);
       }
     }
     SYNC_OR_EXIT();
@@ -1019,7 +1111,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &xm, sl, 1, part, G, rank);
-        hw_reduce_store(L, RB, r, V.x, c0, c1, part, G, rank);
+        hw_reduce_store(L, RB, r, V.x, nullptr, c0, c1, part, G, rank);
       }
     }
     SYNC_OR_EXIT();
