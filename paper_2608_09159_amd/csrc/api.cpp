@@ -296,7 +296,7 @@ int upload_instance(Handle* h, Instance* I) {
     // one per nonempty segment), and each segment is cut by cumulative
     // weight.  Without heavy units this is the plain cumulative split.
     auto split = [&](const std::vector<std::pair<long, double>>& units, const std::vector<char>& heavy_u,
-                     long total_items, std::vector<long>& out) {
+                     const std::vector<signed char>& kind_u, long total_items, std::vector<long>& out) {
       struct Seg { size_t a, b; bool heavy; double w; int k; };
       std::vector<Seg> segs;
       double wlight = 0.0;
@@ -308,7 +308,7 @@ int upload_instance(Handle* h, Instance* I) {
         }
         size_t j = i;
         double w = 0.0;
-        while (j < units.size() && !heavy_u[j]) w += units[j++].second;
+        while (j < units.size() && !heavy_u[j] && kind_u[j] == kind_u[i]) w += units[j++].second;
         segs.push_back({i, j, false, w, 0});
         wlight += w;
         i = j;
@@ -316,7 +316,7 @@ int upload_instance(Handle* h, Instance* I) {
       int nheavy = 0, nlight = 0;
       for (const auto& s : segs) (s.heavy ? nheavy : nlight) += 1;
       int avail = G - nheavy;
-      if (nheavy == 0 || avail < nlight) {
+      if ((nheavy == 0 && nlight <= 1) || avail < nlight) {
         // plain cumulative split (also the fallback when there are too many
         // heavy units for dedicated workgroups)
         double total = 0.0;
@@ -383,8 +383,13 @@ int upload_instance(Handle* h, Instance* I) {
     };
     std::vector<std::pair<long, double>> cu;
     std::vector<char> cheavy;
+    // unit kinds: elementwise coordinates, or the cone type; a workgroup's
+    // range never spans two kinds, so no workgroup runs two kinds of
+    // projection (or mixes SOC and RSOC group widths) one after the other
+    std::vector<signed char> ckind;
     cu.reserve(n);
     cheavy.reserve(n);
+    ckind.reserve(n);
     // a coordinate whose A^T or P row has at least 4096 nonzeros and more
     // than 5% of a workgroup's share of all of them
     const double rownz_total = (double)H.AT.nnz() + (double)(H.P.rows > 0 ? H.P.nnz() : 0);
@@ -408,23 +413,33 @@ int upload_instance(Handle* h, Instance* I) {
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
           cu.emplace_back(i + 1, wcoord(i));
           cheavy.push_back(rownz(i) > heavy_nz);
+          ckind.push_back(0);
         }
       } else {
         double w = 0.0, zmax = 0.0;
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
-          w += wcoord(i) + 16.0 * fq;
+          w += wcoord(i) + 26.0 * fq;
           zmax = std::max(zmax, rownz(i));
         }
-        if (cb.type == PDHCG_CONE_EXP || cb.type == PDHCG_CONE_POW) w += 400.0 * fq;
+        if (cb.type == PDHCG_CONE_EXP) w += 180.0 * fq;
+        if (cb.type == PDHCG_CONE_POW) w += 320.0 * fq;
         cu.emplace_back((long)cb.start + cb.dim, w);
         cheavy.push_back(zmax > heavy_nz);
+        ckind.push_back((signed char)(1 + cb.type));
       }
     }
-    split(cu, cheavy, n, pc);
+    {
+      // with many alternating blocks the kinds would fragment the split:
+      // keep them only while there are few kind runs
+      int runs = 0;
+      for (size_t i = 0; i < ckind.size(); ++i) runs += (i == 0 || ckind[i] != ckind[i - 1]) ? 1 : 0;
+      if (runs > std::max(1, G / 8)) std::fill(ckind.begin(), ckind.end(), (signed char)0);
+    }
+    split(cu, cheavy, ckind, n, pc);
     std::vector<std::pair<long, double>> ru;
     ru.reserve(m);
     for (long l = 0; l < m; ++l) ru.emplace_back(l + 1, 2.0 + (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
-    split(ru, std::vector<char>(ru.size(), 0), m, pr);
+    split(ru, std::vector<char>(ru.size(), 0), std::vector<signed char>(ru.size(), 0), m, pr);
     for (int w = 0; w <= G; ++w) {
       pw[w] = (int)(std::lower_bound(H.wave_start.begin(), H.wave_start.end(), (int)std::min<long>(pc[w], n)) -
                     H.wave_start.begin());
