@@ -112,14 +112,18 @@ struct Batch {
 // lanes per row minimising the dependent memory round trips of one
 // workgroup's pass over `rows` rows of mean length `mean`: each group of rows
 // costs a row-pointer load plus, per four nonzeros of a lane, a column-index
-// and a gathered-value load
-int pick_lanes(double rows, double mean, int maxL = 64) {
+// and a gathered-value load.  With the longest row `maxlen` (default: the
+// mean) one pass costs as much as that row, since the workgroup waits for
+// its slowest group.
+int pick_lanes(double rows, double mean, int maxL = 64, double maxlen = -1.0) {
   int best = 1;
   double bc = 1e300;
+  if (maxlen < mean) maxlen = mean;
   for (int L = 1; L <= maxL; L = (L == 64 ? block_size() : 2 * L)) {
     const double passes = std::ceil(std::max(rows, 1.0) / (double)(block_size() / L));
     const double trips = std::ceil(std::max(mean, 1.0) / (4.0 * L));
-    const double cost = passes * (1.0 + 2.0 * trips) + 0.25 * std::log2((double)L);
+    const double tmax = std::ceil(std::max(maxlen, 1.0) / (4.0 * L));
+    const double cost = (passes - 1.0) * (1.0 + 2.0 * trips) + (1.0 + 2.0 * tmax) + 0.25 * std::log2((double)L);
     if (cost < bc) {
       bc = cost;
       best = L;
@@ -428,18 +432,28 @@ int upload_instance(Handle* h, Instance* I) {
         ckind.push_back((signed char)(1 + cb.type));
       }
     }
-    {
-      // with many alternating blocks the kinds would fragment the split:
-      // keep them only while there are few kind runs
+    // with many alternating kinds the kind boundaries would fragment the
+    // split: keep them only while there are few kind runs
+    auto few_runs = [&](std::vector<signed char>& kind) {
       int runs = 0;
-      for (size_t i = 0; i < ckind.size(); ++i) runs += (i == 0 || ckind[i] != ckind[i - 1]) ? 1 : 0;
-      if (runs > std::max(1, G / 8)) std::fill(ckind.begin(), ckind.end(), (signed char)0);
-    }
+      for (size_t i = 0; i < kind.size(); ++i) runs += (i == 0 || kind[i] != kind[i - 1]) ? 1 : 0;
+      if (runs > std::max(1, G / 8)) std::fill(kind.begin(), kind.end(), (signed char)0);
+    };
+    few_runs(ckind);
     split(cu, cheavy, ckind, n, pc);
+    // rows: weighted by their nonzeros; a workgroup's rows share one length
+    // class (<= 16, 64, 256, 1024 nonzeros, longer) while the classes come in
+    // few runs, so the lanes per row chosen from the mean fit every row
     std::vector<std::pair<long, double>> ru;
+    std::vector<signed char> rkind(m);
     ru.reserve(m);
-    for (long l = 0; l < m; ++l) ru.emplace_back(l + 1, 2.0 + (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
-    split(ru, std::vector<char>(ru.size(), 0), std::vector<signed char>(ru.size(), 0), m, pr);
+    for (long l = 0; l < m; ++l) {
+      const long z = H.A.ptr[l + 1] - H.A.ptr[l];
+      ru.emplace_back(l + 1, 2.0 + (double)z);
+      rkind[l] = (signed char)(z <= 16 ? 0 : (z <= 64 ? 1 : (z <= 256 ? 2 : (z <= 1024 ? 3 : 4))));
+    }
+    few_runs(rkind);
+    split(ru, std::vector<char>(ru.size(), 0), rkind, m, pr);
     for (int w = 0; w <= G; ++w) {
       pw[w] = (int)(std::lower_bound(H.wave_start.begin(), H.wave_start.end(), (int)std::min<long>(pc[w], n)) -
                     H.wave_start.begin());
@@ -451,16 +465,19 @@ int upload_instance(Handle* h, Instance* I) {
     std::vector<unsigned short> lanes(4 * (size_t)G, 1);
     for (int w = 0; w < G; ++w) {
       long nr = pc[w + 1] - pc[w];
-      double nz = 0.0;
+      double nz = 0.0, zmax = 0.0;
       if (nr > 0) {
         nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
         if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
+        for (long i = pc[w]; i < pc[w + 1]; ++i) zmax = std::max(zmax, rownz(i));
       }
       lanes[4 * w + 0] = (unsigned short)(h->s.lanes_at > 0 ? h->s.lanes_at
-                                                          : pick_lanes((double)nr, nr > 0 ? nz / nr : 1.0, block_size()));
+                                                          : pick_lanes((double)nr, nr > 0 ? nz / nr : 1.0,
+                                                                       block_size(), zmax));
       long mr = pr[w + 1] - pr[w];
-      double mz = mr > 0 ? (double)(H.A.ptr[pr[w + 1]] - H.A.ptr[pr[w]]) / mr : 1.0;
-      lanes[4 * w + 1] = (unsigned short)(h->s.lanes_a > 0 ? h->s.lanes_a : pick_lanes((double)mr, mz));
+      double mz = mr > 0 ? (double)(H.A.ptr[pr[w + 1]] - H.A.ptr[pr[w]]) / mr : 1.0, mmax = 0.0;
+      for (long l = pr[w]; l < pr[w + 1]; ++l) mmax = std::max(mmax, (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
+      lanes[4 * w + 1] = (unsigned short)(h->s.lanes_a > 0 ? h->s.lanes_a : pick_lanes((double)mr, mz, 64, mmax));
       int maxdim = 1;
       for (int it = pw[w]; it < pw[w + 1]; ++it) maxdim = std::max(maxdim, H.wave_dim[it]);
       lanes[4 * w + 2] = (unsigned short)(maxdim <= 17 ? 16 : (maxdim <= 33 ? 32 : 64));
@@ -529,6 +546,16 @@ int upload_instance(Handle* h, Instance* I) {
     P.part_w = B.upload(pw);
     P.part_l = B.upload(pl);
     P.part_lanes = B.upload(lanes);
+    if (const char* path = std::getenv("PDHCG_PARTITION_DUMP")) {
+      // one line per workgroup: coordinate range, row range, lanes per A^T
+      // row, per A row, SOC group width
+      if (FILE* f = std::fopen(path, "w")) {
+        for (int w = 0; w < G; ++w)
+          std::fprintf(f, "%d %ld %ld %ld %ld %d %d %d\n", w, pc[w], pc[w + 1], pr[w], pr[w + 1], lanes[4 * w],
+                       lanes[4 * w + 1], lanes[4 * w + 2]);
+        std::fclose(f);
+      }
+    }
   }
   V.partials = B.alloc<double>((size_t)SL_COUNT * G);
   I->bar_bytes = sizeof(Barrier) + sizeof(unsigned) * (size_t)G * BAR_STRIDE;
