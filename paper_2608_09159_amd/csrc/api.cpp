@@ -786,8 +786,8 @@ void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D)
 // lanes per row for rows of mean length `mean`: a power of two <= mean/div;
 // div = 0 selects the round-trip model of the single-problem path (with the
 // whole instance on one workgroup)
-int lanes_rule(double rows, double mean, int div) {
-  if (div <= 0) return pick_lanes(rows, mean);
+int lanes_rule(double rows, double mean, int div, double maxlen = -1.0) {
+  if (div <= 0) return pick_lanes(rows, mean, 64, maxlen);
   int L = 1;
   while (L * 2 <= std::max(1.0, mean / div) && L < 64) L *= 2;
   return L;
@@ -801,8 +801,16 @@ void set_lanes(Handle* h, int div_a, int div_at) {
     if (H.P.rows > 0) nz_at = std::max<int64_t>(nz_at, H.P.nnz());
     const double mat = H.n > 0 ? (double)nz_at / H.n : 1.0;
     const double ma = H.m > 0 ? (double)H.A.nnz() / H.m : 1.0;
-    B->desc[i].la = h->s.lanes_at > 0 ? h->s.lanes_at : lanes_rule((double)H.n, mat, div_at);
-    B->desc[i].lr = h->s.lanes_a > 0 ? h->s.lanes_a : lanes_rule((double)H.m, ma, div_a);
+    // longest rows, as the single-solve partition prices them
+    double zat = 0.0, za = 0.0;
+    for (long j = 0; j < H.n; ++j) {
+      double z = (double)(H.AT.ptr[j + 1] - H.AT.ptr[j]);
+      if (H.P.rows > 0) z = std::max(z, (double)(H.P.ptr[j + 1] - H.P.ptr[j]));
+      zat = std::max(zat, z);
+    }
+    for (long l = 0; l < H.m; ++l) za = std::max(za, (double)(H.A.ptr[l + 1] - H.A.ptr[l]));
+    B->desc[i].la = h->s.lanes_at > 0 ? h->s.lanes_at : lanes_rule((double)H.n, mat, div_at, zat);
+    B->desc[i].lr = h->s.lanes_a > 0 ? h->s.lanes_a : lanes_rule((double)H.m, ma, div_a, za);
   }
   B->div_a = div_a;
   B->div_at = div_at;

@@ -33,6 +33,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "cones.hpp"
@@ -48,6 +49,7 @@ struct Lds {
   double scal[SL_COUNT];
   double ht[RMAX];       // D^ h for the Q product of the current pass
   double Dl[RMAX * RMAX];  // D^ (r x r), staged once per run
+  double hw[NWAVE][RMAX];   // per-wave R^ u accumulators (single-workgroup teams)
   double hu[RMAX];       // R^ u of the current inner iterate
   double hs[RMAX];       // R^ s, s = u - u_prev (one-sync inner step)
   Ctl C;
@@ -183,6 +185,37 @@ struct RSrc {
     return l ? l[(size_t)k * nl + (i - c0)] : g[(size_t)k * n + i];
   }
 };
+
+// Single-workgroup teams (the batch kernels, a grid of one) accumulate R v
+// inside the coordinate passes: hw_clear, then hw_add per coordinate chunk
+// (one wave sum per factor row, into per-wave accumulators), then hw_store
+// sums the waves into the partial slots.  Grids use hw_reduce_store below.
+__device__ __forceinline__ void hw_clear(Lds& L) {
+  for (int i = threadIdx.x; i < NWAVE * RMAX; i += BLOCK) (&L.hw[0][0])[i] = 0.0;
+  __syncthreads();
+}
+
+// wave-uniform: add R[k, i] * val (0 if !active) to the wave's accumulators
+// (the product in the factor's precision, the sums in FP64)
+template <class MV>
+__device__ __forceinline__ void hw_add(Lds& L, const RSrc<MV>& R, int r, long i, double val, bool active) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < r; ++k) {
+    double t = active ? (double)(R(k, i) * (MV)val) : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) L.hw[wv][k] += t;
+  }
+}
+
+__device__ __forceinline__ void hw_store(Lds& L, int r, double* partials, int G, int rank) {
+  __syncthreads();
+  if ((int)threadIdx.x < r) {
+    double s = 0.0;
+    for (int w = 0; w < NWAVE; ++w) s += L.hw[w][threadIdx.x];
+    partials[(size_t)(SL_H0 + threadIdx.x) * G + rank] = s;
+  }
+  __syncthreads();
+}
 
 // the workgroup's share of R v over its coordinates [c0, c1) into the
 // partial slots SL_H0 + k, and with vp also R (v - vp) into SL_HS0 + k: one
@@ -618,25 +651,41 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     tmark(L, prof, _pc);                            \
   } while (0)
 
+  // single-workgroup teams (the batch kernels, a grid of one) keep the
+  // in-pass R v accumulation and two synchronisations per inner step: their
+  // synchronisations are workgroup barriers, and in-pass accumulation reads
+  // nothing back
+  constexpr bool SOLO = std::is_same<Team, SoloTeam>::value;
+  const bool fuse = !SOLO && !P.q_diag && (P.p_diag || !P.P_ptr);
+  // the R v partial of this workgroup after a coordinate pass that wrote v
+  // (and R (v - vp) for the one-sync inner step)
+  auto hw_finish = [&](const auto& R, const double* v, const double* vp) {
+    if constexpr (SOLO) hw_store(L, r, part, G, rank);
+    else hw_reduce_store(L, R, r, v, vp, c0, c1, part, G, rank);
+  };
+
   for (int e = tid; e < r * r; e += BLOCK) L.Dl[e] = P.Dm[e];
   __syncthreads();
 
   // ------------------------------------------------------------------ init
   if (!L.C.started) {
     // x = Pi_K(x0^) (zb holds the scaled warm start or zeros); a_x = x
+    if constexpr (SOLO) hw_clear(L);
     for_range(c0, c1, [&](long i, bool act) {
       bool el = act && P.ctype[i] != CT_CONE;
       double x = el ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
       if (el) { V.x[i] = x; V.ax[i] = x; }
+      if constexpr (SOLO) hw_add(L, R64, r, i, x, el);
     });
     if (has_items) {
       project_items(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
       for_item_coords(P, IT, [&](long i, bool act) {
         double x = act ? V.zb[i] : 0.0;
         if (act) { V.x[i] = x; V.ax[i] = x; }
+        if constexpr (SOLO) hw_add(L, R64, r, i, x, act);
       });
     }
-    hw_reduce_store(L, R64, r, V.x, nullptr, c0, c1, part, G, rank);
+    hw_finish(R64, V.x, nullptr);
     SYNC_OR_EXIT();
     for_rows_range(r0, r1, own.lr, [&](long row, int sub, bool act) {
       double ax = spmv_row(P.A_ptr, P.A_col, P.A_val, V.x, row, sub, own.lr, act);
@@ -667,7 +716,6 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   const bool jac = S.inner == PDHCG_INNER_JACOBI;
   // P diagonal or absent: one grid synchronisation per inner step (a sparse
   // P needs the neighbours' s for <s, P s>: two)
-  const bool fuse = !P.q_diag && (P.p_diag || !P.P_ptr);
   const double rho = S.rho;
   const int La = own.la, Lr = own.lr;
 
@@ -717,7 +765,10 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       // acc: ||s||^2, <s, M s>, <s, P s> of the first step s = u - x (the
       // last two for the one-sync inner step only)
       double acc[3] = {0.0, 0.0, 0.0};
+      if constexpr (SOLO) hw_clear(L);
       for_range(c0, c1, [&](long i, bool act) {
+        double un = 0.0;
+        bool el = false;
         if (act) {
           const double xi = V.x[i];
           const double vi = xi + tau * V.t1[i];
@@ -730,7 +781,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           if (!fuse) V.gp[i] = g0;
           V.up[i] = xi;
           if (P.ctype[i] != CT_CONE) {
-            const double un = elem_proj(P.ctype[i], z);
+            el = true;
+            un = elem_proj(P.ctype[i], z);
             V.u[i] = un;
             const double si = un - xi;
             acc[0] += si * si;
@@ -742,13 +794,15 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.zb[i] = z;
           }
         }
+        if constexpr (SOLO) hw_add(L, RB, r, i, un, el);
       });
       if (has_items) {
         __syncthreads();
         PROJ(project_items(P, IT, !jac, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb, V.warm));
         for_item_coords(P, IT, [&](long i, bool act) {
+          double un = 0.0;
           if (act) {
-            const double un = V.zb[i];
+            un = V.zb[i];
             V.u[i] = un;
             const double si = un - V.up[i];
             acc[0] += si * si;
@@ -757,12 +811,12 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
               if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
             }
           }
+          if constexpr (SOLO) hw_add(L, RB, r, i, un, act);
         });
       }
       const int sl[3] = {SL_DELTA2, SL_SJS, SL_SPS};
       block_store(L, acc, sl, fuse ? 3 : 1, part, G, rank);
-      if (fuse) hw_reduce_store(L, RB, r, V.u, V.up, c0, c1, part, G, rank);
-      else hw_reduce_store(L, RB, r, V.u, nullptr, c0, c1, part, G, rank);
+      hw_finish(RB, V.u, fuse ? V.up : nullptr);
     }
     SYNC_OR_EXIT();
 
@@ -829,34 +883,37 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         // ---- P4: projected step (fuse: the gradient is formed here)
         tmark(L, prof, PT_P4);
         double acc[3] = {0.0, 0.0, 0.0};
+        if constexpr (SOLO) hw_clear(L);
         for_range(c0, c1, [&](long i, bool act) {
-          if (!act) return;
-          const bool el = P.ctype[i] != CT_CONE;
-          const double ui = V.u[i];
-          double gi;
-          if (fuse) {
-            const double ru = r_dot(RB, r, i, L.ht);
-            const double pu = P.p_diag ? P.Pd[i] * ui : 0.0;
-            gi = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
-            if (!el) V.g[i] = gi;
-          } else {
-            if (!el) return;
-            gi = V.g[i];
-          }
-          if (el) {
-            const double mi = Mq(i);
-            const double un = elem_proj(P.ctype[i], ui - alpha * gi / mi);
-            const double si = un - ui;
-            acc[0] += si * si;
+          const bool el = act && P.ctype[i] != CT_CONE;
+          double un = 0.0;
+          if (act && (el || fuse)) {
+            const double ui = V.u[i];
+            double gi;
             if (fuse) {
-              acc[1] += si * (mi * si);
-              if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+              const double ru = r_dot(RB, r, i, L.ht);
+              const double pu = P.p_diag ? P.Pd[i] * ui : 0.0;
+              gi = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
+              if (!el) V.g[i] = gi;
             } else {
-              V.gp[i] = gi;
+              gi = V.g[i];
             }
-            V.up[i] = ui;
-            V.u[i] = un;
+            if (el) {
+              const double mi = Mq(i);
+              un = elem_proj(P.ctype[i], ui - alpha * gi / mi);
+              const double si = un - ui;
+              acc[0] += si * si;
+              if (fuse) {
+                acc[1] += si * (mi * si);
+                if (P.p_diag) acc[2] += si * (P.Pd[i] * si);
+              } else {
+                V.gp[i] = gi;
+              }
+              V.up[i] = ui;
+              V.u[i] = un;
+            }
           }
+          if constexpr (SOLO) hw_add(L, RB, r, i, un, el);
         });
         if (has_items) {
           if (fuse) __syncthreads();
@@ -864,8 +921,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
                              [&](long st) { return StepSrc{V.u, V.g, Mq, alpha, st}; }, V.zb, V.warm,
                              prof ? &L.pt[PT_WCALL] : nullptr));
           for_item_coords(P, IT, [&](long i, bool act) {
+            double un = 0.0;
             if (act) {
-              const double un = V.zb[i];
+              un = V.zb[i];
               const double ui = V.u[i];
               const double si = un - ui;
               acc[0] += si * si;
@@ -878,13 +936,13 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
               V.up[i] = ui;
               V.u[i] = un;
             }
+            if constexpr (SOLO) hw_add(L, RB, r, i, un, act);
           });
         }
         {
           const int sl[3] = {SL_DELTA2, SL_SJS, SL_SPS};
           block_store(L, acc, sl, fuse ? 3 : 1, part, G, rank);
-          if (fuse) hw_reduce_store(L, RB, r, V.u, V.up, c0, c1, part, G, rank);
-          else hw_reduce_store(L, RB, r, V.u, nullptr, c0, c1, part, G, rank);
+          hw_finish(RB, V.u, fuse ? V.up : nullptr);
         }
         SYNC_OR_EXIT();
         if (fuse) {
@@ -930,6 +988,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           }
         }
       });
+      if constexpr (SOLO) {
+        if (!check) hw_clear(L);
+      }
       for_range(c0, c1, [&](long i, bool act) {
         double xn = 0.0;
         if (act) {
@@ -947,6 +1008,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
+        if constexpr (SOLO) {
+          if (!check) hw_add(L, RB, r, i, xn, act);
+        }
       });
       if (check) {
         const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
@@ -954,7 +1018,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       } else {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &acc[5], sl, 1, part, G, rank);
-        hw_reduce_store(L, RB, r, V.x, nullptr, c0, c1, part, G, rank);
+        hw_finish(RB, V.x, nullptr);
       }
     }
     SYNC_OR_EXIT();
@@ -1085,6 +1149,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     tmark(L, prof, PT_HALP);
     {
       double xm = 0.0;
+      if constexpr (SOLO) {
+        if (!restart) hw_clear(L);
+      }
       for (long l = r0 + tid; l < r1; l += BLOCK) {
         const double wy = V.wy[l], aw = V.Aw[l];
         if (restart) {
@@ -1107,11 +1174,14 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             V.x[i] = xn;
           }
         }
+        if constexpr (SOLO) {
+          if (!restart) hw_add(L, RB, r, i, xn, act);
+        }
       });
       if (!restart) {
         const int sl[1] = {SL_XMOV2};
         block_store(L, &xm, sl, 1, part, G, rank);
-        hw_reduce_store(L, RB, r, V.x, nullptr, c0, c1, part, G, rank);
+        hw_finish(RB, V.x, nullptr);
       }
     }
     SYNC_OR_EXIT();
@@ -1137,7 +1207,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
 // ---------------------------------------------------------------------------
 // single-problem kernel: the whole grid is one team
 // ---------------------------------------------------------------------------
-template <class MV>
+template <class MV, bool SOLO>
 __device__ void solve_body(const KArgs& A) {
   __shared__ Lds L;
   const int rank = blockIdx.x, G = gridDim.x;
@@ -1163,20 +1233,28 @@ __device__ void solve_body(const KArgs& A) {
   own.lr = P.part_lanes[4 * rank + 1];
   own.atperm = P.at_perm;
   own.atseg = P.at_perm ? P.at_seg + (kClasses + 1) * rank : nullptr;
-  GridTeam T{A.bar, A.spin_limit, rank, G};
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull, A.lds_bytes > 0 ? dyn_lds : nullptr, A.lds_bytes};
-  run_solver<true, MV>(run, P, A.V, A.ctl, T, L, own, prof);
+  if constexpr (SOLO) {
+    run_solver<true, MV>(run, P, A.V, A.ctl, SoloTeam{}, L, own, prof);
+  } else {
+    GridTeam T{A.bar, A.spin_limit, rank, G};
+    run_solver<true, MV>(run, P, A.V, A.ctl, T, L, own, prof);
+  }
   tmark(L, prof, PT_INIT);
   __syncthreads();
   if (prof && threadIdx.x < PT_COUNT) A.ptimes[(size_t)rank * PT_COUNT + threadIdx.x] += L.pt[threadIdx.x];
   if (rank == 0 && threadIdx.x == 0 && L.C.status != PDHCG_ABORTED) *A.ctl = L.C;
 }
 
-__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<double>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<double, false>(A); }
 
 // FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
-__global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false>(A); }
+
+// a grid of one workgroup: workgroup barriers and the single-workgroup
+// reductions of the batch kernels (the same arithmetic as a batch solve)
+__global__ __launch_bounds__(BLOCK) void solve_kernel_one(KArgs A) { solve_body<double, true>(A); }
 
 // ---------------------------------------------------------------------------
 // setup kernels: CSR SpMV and deterministic two-pass norms (power iteration)
@@ -1390,7 +1468,8 @@ int block_size() { return BLOCK; }
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream) {
   KArgs a = args;
   void* params[] = {&a};
-  const void* k = fp32 ? (const void*)solve_kernel_f32 : (const void*)solve_kernel;
+  const void* k = fp32 ? (const void*)solve_kernel_f32
+                       : (grid == 1 ? (const void*)solve_kernel_one : (const void*)solve_kernel);
   return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BLOCK), params, (size_t)args.lds_bytes, stream);
 }
 
