@@ -460,8 +460,23 @@ int upload_instance(Handle* h, Instance* I) {
       pl[w] = (int)(std::lower_bound(H.lane_start.begin(), H.lane_start.end(), (int)std::min<long>(pc[w], n)) -
                     H.lane_start.begin());
     }
+    // skewed A^T row lengths (some row of a workgroup more than 16 times its
+    // mean and longer than 64): A^T rows then run in length classes (below)
+    bool at_classes = false;
+    for (int w = 0; w < G && !at_classes; ++w) {
+      const long nr = pc[w + 1] - pc[w];
+      if (nr <= 0) continue;
+      const double mean = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]) / nr;
+      for (long i = pc[w]; i < pc[w + 1]; ++i) {
+        const double z = (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+        if (z > 64.0 && z > 16.0 * mean) { at_classes = true; break; }
+      }
+    }
+    at_classes = at_classes && h->s.lanes_at <= 0;
     // lanes per row chosen per workgroup from its own rows (about two
-    // nonzeros per lane), SOC/RSOC group width from its longest block
+    // nonzeros per lane; the longest row priced in, of A^T only when A^T
+    // does not run in length classes), SOC/RSOC group width from its longest
+    // block
     std::vector<unsigned short> lanes(4 * (size_t)G, 1);
     for (int w = 0; w < G; ++w) {
       long nr = pc[w + 1] - pc[w];
@@ -469,7 +484,11 @@ int upload_instance(Handle* h, Instance* I) {
       if (nr > 0) {
         nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
         if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
-        for (long i = pc[w]; i < pc[w + 1]; ++i) zmax = std::max(zmax, rownz(i));
+        for (long i = pc[w]; i < pc[w + 1]; ++i) {
+          double z = H.P.rows > 0 ? (double)(H.P.ptr[i + 1] - H.P.ptr[i]) : 0.0;
+          if (!at_classes) z = std::max(z, (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]));
+          zmax = std::max(zmax, z);
+        }
       }
       lanes[4 * w + 0] = (unsigned short)(h->s.lanes_at > 0 ? h->s.lanes_at
                                                           : pick_lanes((double)nr, nr > 0 ? nz / nr : 1.0,
@@ -494,17 +513,7 @@ int upload_instance(Handle* h, Instance* I) {
     P.at_perm = nullptr;
     P.at_seg = nullptr;
     {
-      bool skew = false;
-      for (int w = 0; w < G && !skew; ++w) {
-        const long nr = pc[w + 1] - pc[w];
-        if (nr <= 0) continue;
-        const double mean = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]) / nr;
-        for (long i = pc[w]; i < pc[w + 1]; ++i) {
-          const double z = (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
-          if (z > 64.0 && z > 16.0 * mean) { skew = true; break; }
-        }
-      }
-      if (skew && h->s.lanes_at <= 0) {
+      if (at_classes) {
         constexpr int NC = 5;
         std::vector<int> perm(n), seg((size_t)(NC + 1) * G);
         for (int w = 0; w < G; ++w) {
