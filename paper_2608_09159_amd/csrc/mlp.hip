@@ -5,11 +5,11 @@
 // GEMM: C[M x N] = op(A)[M x K] * op(B)[K x N], all matrices row-major.
 //   A: M x K (TA = false) or stored K x M (TA = true, used transposed)
 //   B: K x N (TB = false) or stored N x K (TB = true, used transposed)
-// Workgroup tile 64 x 64 x 32, four waves, each wave one 32 x 32 output
-// block computed with v_mfma_f32_32x32x16_bf16 (two per K step).  Both
+// Workgroup tile 128 x 128 x TK, four waves, each wave a 64 x 64 output block
+// (2 x 2 blocks of v_mfma_f32_32x32x16_bf16, TK / 16 steps per stage).  Both
 // operand tiles are staged in LDS with K contiguous (row stride padded by 8
 // elements), so every lane reads its 8-element fragment with one 16-byte LDS
-// load.  Long K is split over `splits` workgroups writing FP32 partial tiles;
+// load; global loads are 8-byte runs along the contiguous dimension.  Long K is split over `splits` workgroups writing FP32 partial tiles;
 // a second kernel sums them in a fixed order and applies the epilogue, so
 // results do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -26,7 +26,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int TM = 128, TN = 128, TK = 32, LDK = TK + 8;
+constexpr int TM = 128, TN = 128, TK = 64, LDK = TK + 8;
 constexpr int GT = 256;   // threads per GEMM workgroup (4 waves, 2 x 2 of 64 x 64)
 constexpr int VW = 4;     // elements per vector load (8 bytes)
 
@@ -72,6 +72,14 @@ __device__ __forceinline__ bf16x4 load_run(const __bf16* src, int lim, bool vec)
   return v;
 }
 
+// LDS column of element (row r, k): the 8-element k groups of a row are
+// XOR-permuted by (r / 16) so that both the staging writes and the
+// fragment reads spread over the banks (2-way and 4-way, the minimum for
+// 8- and 16-byte accesses of a wave)
+__device__ __forceinline__ int kswz(int r, int k) {
+  return ((((k >> 3) ^ (r >> 4)) & (TK / 8 - 1)) << 3) | (k & 7);
+}
+
 // stage one operand tile of R rows (m or n) x TK (k) into S[row][k]:
 // k-contiguous storage (element (r, k) at P[r * ld + k]) or r-contiguous
 // storage (element (r, k) at P[k * ld + r])
@@ -81,29 +89,37 @@ __device__ __forceinline__ void stage(__bf16 (*S)[LDK], const __bf16* P, long ld
   const int tid = threadIdx.x;
   const __bf16 zero = (__bf16)0.0f;
   if (KCONTIG) {
-    // 128 rows x 8 runs of 4 k
+    // 128 rows x TK / VW runs of VW k
+    constexpr int RUNS = TK / VW;
 #pragma unroll
     for (int q = 0; q < (TM * TK / VW) / GT; ++q) {
       const int v = tid + q * GT;
-      const int r = v >> 3, kq = (v & 7) * VW;
+      const int r = v / RUNS, kq = (v % RUNS) * VW;
       const int row = r0 + r, k = k0 + kq;
       bf16x4 x;
       if (row < rmax && k < kend) x = load_run(P + (size_t)row * ld + k, kend - k, vec);
       else x = bf16x4{zero, zero, zero, zero};
-      *reinterpret_cast<bf16x4*>(&S[r][kq]) = x;
+      *reinterpret_cast<bf16x4*>(&S[r][kswz(r, kq)]) = x;
     }
   } else {
-    // 32 k x 32 runs of 4 rows
+    // 4 x 4 blocks (4 rows x 4 k): four runs of 4 rows along the contiguous
+    // dimension, transposed in registers into four runs of 4 k
+    constexpr int RB = TM / 4;
 #pragma unroll
-    for (int q = 0; q < (TM * TK / VW) / GT; ++q) {
-      const int v = tid + q * GT;
-      const int kk = v >> 5, rq = (v & 31) * VW;
-      const int row = r0 + rq, k = k0 + kk;
-      bf16x4 x;
-      if (row < rmax && k < kend) x = load_run(P + (size_t)k * ld + row, rmax - row, vec);
-      else x = bf16x4{zero, zero, zero, zero};
+    for (int q = 0; q < (TM / 4) * (TK / 4) / GT; ++q) {
+      const int b = tid + q * GT;
+      const int rb = (b % RB) * 4, kb = (b / RB) * 4;
+      const int row = r0 + rb;
+      bf16x4 x[4];
 #pragma unroll
-      for (int j = 0; j < VW; ++j) S[rq + j][kk] = x[j];
+      for (int t = 0; t < 4; ++t) {
+        const int k = k0 + kb + t;
+        if (row < rmax && k < kend) x[t] = load_run(P + (size_t)k * ld + row, rmax - row, vec);
+        else x[t] = bf16x4{zero, zero, zero, zero};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<bf16x4*>(&S[rb + j][kswz(rb + j, kb)]) = bf16x4{x[0][j], x[1][j], x[2][j], x[3][j]};
     }
   }
 }
@@ -128,8 +144,9 @@ __global__ __launch_bounds__(GT) void gemm_kernel(GemmArgs g) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + (lane & 31)][ks + (lane >> 5) * 8]);
-        b[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * i + (lane & 31)][ks + (lane >> 5) * 8]);
+        const int ra = wm + 32 * i + (lane & 31), rb = wn + 32 * i + (lane & 31);
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[ra][kswz(ra, ks + (lane >> 5) * 8)]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&Bs[rb][kswz(rb, ks + (lane >> 5) * 8)]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
