@@ -242,30 +242,6 @@ __global__ __launch_bounds__(256) void adam_kernel(float* w, __bf16* wb, const f
   }
 }
 
-// the same update on four consecutive elements per thread (16-byte loads and
-// stores; all pointers 16-byte aligned, n4 = n / 4 groups)
-__global__ __launch_bounds__(256) void adam4_kernel(float* w, __bf16* wb, const float* g, float* m, float* v,
-                                                   long n4, AdamStep a) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long)gridDim.x * 256) {
-    const f4 gi = reinterpret_cast<const f4*>(g)[i];
-    const f4 m0 = reinterpret_cast<const f4*>(m)[i];
-    const f4 v0 = reinterpret_cast<const f4*>(v)[i];
-    const f4 w0 = reinterpret_cast<const f4*>(w)[i];
-    f4 mi, vi, wi;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      mi[j] = a.b1 * m0[j] + a.omb1 * gi[j];
-      vi[j] = a.b2 * v0[j] + a.omb2 * gi[j] * gi[j];
-      wi[j] = w0[j] - a.lr * (mi[j] / a.c1) / (sqrtf(vi[j] / a.c2) + a.eps);
-    }
-    reinterpret_cast<f4*>(m)[i] = mi;
-    reinterpret_cast<f4*>(v)[i] = vi;
-    reinterpret_cast<f4*>(w)[i] = wi;
-    if (wb) reinterpret_cast<bf16x4*>(wb)[i] = bf16x4{(__bf16)wi[0], (__bf16)wi[1], (__bf16)wi[2], (__bf16)wi[3]};
-  }
-}
-
 int grid_for(long n, int per, int cap) {
   long g = (n + per - 1) / per;
   return (int)std::max<long>(1, std::min<long>(g, cap));
@@ -293,10 +269,11 @@ hipError_t mlp_gemm(const __bf16* A, bool ta, long lda, const __bf16* B, bool tb
   g.outf = outf;
   g.outb = outb;
   const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  // split K until there are about 1024 workgroups (and the partials fit)
+  // split K while the grid stays within one round of resident workgroups
+  // (three per CU) and the partials fit
   const int ksteps = std::max(1, (K + TK - 1) / TK);
   int splits = 1;
-  while (tiles * splits < 1024 && splits * 2 <= ksteps &&
+  while (tiles * splits * 2 <= 768 && splits * 2 <= ksteps &&
          (size_t)(splits * 2) * (size_t)M * (size_t)N <= work_floats)
     splits *= 2;
   const int per = (ksteps + splits - 1) / splits;
@@ -346,17 +323,7 @@ hipError_t mlp_colsum(const __bf16* dz, int rows, int N, float* db, hipStream_t 
 hipError_t mlp_adam(float* w, __bf16* wb, const float* g, float* m, float* v, long n, const AdamStep& a,
                     hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  auto al = [](const void* p, uintptr_t b) { return p == nullptr || ((uintptr_t)p % b) == 0; };
-  const long n4 = n / 4;
-  if (n4 > 0 && al(w, 16) && al(g, 16) && al(m, 16) && al(v, 16) && al(wb, 8)) {
-    hipLaunchKernelGGL(adam4_kernel, dim3(grid_for(n4, 256, 8192)), dim3(256), 0, st, w, wb, g, m, v, n4, a);
-    const long done = n4 * 4;
-    if (done < n)
-      hipLaunchKernelGGL(adam_kernel, dim3(1), dim3(256), 0, st, w + done, wb ? wb + done : nullptr, g + done,
-                         m + done, v + done, n - done, a);
-  } else {
-    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, w, wb, g, m, v, n, a);
-  }
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, w, wb, g, m, v, n, a);
   return hipGetLastError();
 }
 
