@@ -80,46 +80,66 @@ __device__ __forceinline__ int kswz(int r, int k) {
   return ((((k >> 3) ^ (r >> 4)) & (TK / 8 - 1)) << 3) | (k & 7);
 }
 
-// stage one operand tile of R rows (m or n) x TK (k) into S[row][k]:
-// k-contiguous storage (element (r, k) at P[r * ld + k]) or r-contiguous
-// storage (element (r, k) at P[k * ld + r])
+// one operand tile of R rows (m or n) x TK (k), staged through registers:
+// k-contiguous storage (element (r, k) at P[r * ld + k]) as VW-runs of k;
+// r-contiguous storage (element (r, k) at P[k * ld + r]) as 4 x 4 blocks,
+// four runs of 4 rows transposed in registers into four runs of 4 k.
+constexpr int NRUN = (TM * TK / VW) / GT;   // runs of VW elements per thread
+static_assert((TM / 4) * (TK / 4) / GT * 4 == NRUN, "both staging forms use NRUN runs per thread");
+
+// global -> registers (zero outside the matrix or past kend)
 template <bool KCONTIG>
-__device__ __forceinline__ void stage(__bf16 (*S)[LDK], const __bf16* P, long ld, int r0, int rmax, int k0,
-                                      int kend, bool vec) {
+__device__ __forceinline__ void stage_load(bf16x4 (&x)[NRUN], const __bf16* P, long ld, int r0, int rmax,
+                                           int k0, int kend, bool vec) {
   const int tid = threadIdx.x;
   const __bf16 zero = (__bf16)0.0f;
   if (KCONTIG) {
-    // 128 rows x TK / VW runs of VW k
     constexpr int RUNS = TK / VW;
 #pragma unroll
-    for (int q = 0; q < (TM * TK / VW) / GT; ++q) {
+    for (int q = 0; q < NRUN; ++q) {
       const int v = tid + q * GT;
-      const int r = v / RUNS, kq = (v % RUNS) * VW;
-      const int row = r0 + r, k = k0 + kq;
-      bf16x4 x;
-      if (row < rmax && k < kend) x = load_run(P + (size_t)row * ld + k, kend - k, vec);
-      else x = bf16x4{zero, zero, zero, zero};
-      *reinterpret_cast<bf16x4*>(&S[r][kswz(r, kq)]) = x;
+      const int row = r0 + v / RUNS, k = k0 + (v % RUNS) * VW;
+      if (row < rmax && k < kend) x[q] = load_run(P + (size_t)row * ld + k, kend - k, vec);
+      else x[q] = bf16x4{zero, zero, zero, zero};
     }
   } else {
-    // 4 x 4 blocks (4 rows x 4 k): four runs of 4 rows along the contiguous
-    // dimension, transposed in registers into four runs of 4 k
     constexpr int RB = TM / 4;
 #pragma unroll
-    for (int q = 0; q < (TM / 4) * (TK / 4) / GT; ++q) {
+    for (int q = 0; q < NRUN / 4; ++q) {
       const int b = tid + q * GT;
-      const int rb = (b % RB) * 4, kb = (b / RB) * 4;
-      const int row = r0 + rb;
-      bf16x4 x[4];
+      const int row = r0 + (b % RB) * 4, kb = k0 + (b / RB) * 4;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int k = k0 + kb + t;
-        if (row < rmax && k < kend) x[t] = load_run(P + (size_t)k * ld + row, rmax - row, vec);
-        else x[t] = bf16x4{zero, zero, zero, zero};
+        const int k = kb + t;
+        if (row < rmax && k < kend) x[4 * q + t] = load_run(P + (size_t)k * ld + row, rmax - row, vec);
+        else x[4 * q + t] = bf16x4{zero, zero, zero, zero};
       }
+    }
+  }
+}
+
+// registers -> S[row][k] (swizzled k groups)
+template <bool KCONTIG>
+__device__ __forceinline__ void stage_store(__bf16 (*S)[LDK], const bf16x4 (&x)[NRUN]) {
+  const int tid = threadIdx.x;
+  if (KCONTIG) {
+    constexpr int RUNS = TK / VW;
+#pragma unroll
+    for (int q = 0; q < NRUN; ++q) {
+      const int v = tid + q * GT;
+      const int r = v / RUNS, kq = (v % RUNS) * VW;
+      *reinterpret_cast<bf16x4*>(&S[r][kswz(r, kq)]) = x[q];
+    }
+  } else {
+    constexpr int RB = TM / 4;
+#pragma unroll
+    for (int q = 0; q < NRUN / 4; ++q) {
+      const int b = tid + q * GT;
+      const int rb = (b % RB) * 4, kb = (b / RB) * 4;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        *reinterpret_cast<bf16x4*>(&S[rb + j][kswz(rb + j, kb)]) = bf16x4{x[0][j], x[1][j], x[2][j], x[3][j]};
+        *reinterpret_cast<bf16x4*>(&S[rb + j][kswz(rb + j, kb)]) =
+            bf16x4{x[4 * q][j], x[4 * q + 1][j], x[4 * q + 2][j], x[4 * q + 3][j]};
     }
   }
 }
@@ -134,10 +154,20 @@ __global__ __launch_bounds__(GT) void gemm_kernel(GemmArgs g) {
   const int ke = min(g.K, kb + g.kchunk);
   const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
   f32x16 acc[2][2] = {};
+  // the next stage's global loads are in flight while this stage computes
+  bf16x4 xa[NRUN], xb[NRUN];
+  if (kb < ke) {
+    stage_load<!TA>(xa, g.A, g.lda, m0, g.M, kb, ke, g.vec_a != 0);
+    stage_load<TB>(xb, g.B, g.ldb, n0, g.N, kb, ke, g.vec_b != 0);
+  }
   for (int k0 = kb; k0 < ke; k0 += TK) {
-    stage<!TA>(As, g.A, g.lda, m0, g.M, k0, ke, g.vec_a != 0);
-    stage<TB>(Bs, g.B, g.ldb, n0, g.N, k0, ke, g.vec_b != 0);
+    stage_store<!TA>(As, xa);
+    stage_store<TB>(Bs, xb);
     __syncthreads();
+    if (k0 + TK < ke) {
+      stage_load<!TA>(xa, g.A, g.lda, m0, g.M, k0 + TK, ke, g.vec_a != 0);
+      stage_load<TB>(xb, g.B, g.ldb, n0, g.N, k0 + TK, ke, g.vec_b != 0);
+    }
     // lane l holds row/col (l % 32), k (l / 32) * 8 + j of each 32 x 32 x 16 step
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 16) {
