@@ -62,6 +62,54 @@ def test_iterate_parity_skewed_columns():
     trace_parity(synth.large_sparse_qp(seed=1, n=60_000, m=30_000), iters=20)
 
 
+def _partition_dump(prob, tmp_path, **kw):
+    """Set up `prob` with the partition dump on; returns the rows
+    (workgroup, c0, c1, r0, r1, lanes_at, lanes_a, group width)."""
+    import os
+    path = str(tmp_path / "partition.txt")
+    os.environ["PDHCG_PARTITION_DUMP"] = path
+    try:
+        G.setup(prob, **kw).free()
+    finally:
+        del os.environ["PDHCG_PARTITION_DUMP"]
+    return np.loadtxt(path, dtype=np.int64, ndmin=2)
+
+
+def test_iterate_parity_kind_partition(tmp_path):
+    """Many workgroups on the mixed-cone family: each cone kind (SOC, RSOC,
+    EXP, POW, R+) gets workgroups of its own (checked on the partition), and
+    the iterates still match the oracle (one-sync inner steps across 48
+    workgroups)."""
+    p = synth.mixed_cone_scaled(seed=6, scale=0.02)
+    part = _partition_dump(p, tmp_path, grid_dim=48)
+    kind = np.zeros(p.n, dtype=int)
+    codes = {"free": 0, "nonneg": 0, "soc": 1, "rsoc": 2, "exp": 3, "pow": 4}
+    for c in p.cones:
+        kind[c[1]:c[1] + c[2]] = codes[c[0]]
+    for w, c0, c1 in part[:, :3]:
+        if c1 > c0:
+            assert len(set(kind[c0:c1])) == 1, (w, c0, c1)
+    trace_parity(p, grid_dim=48, iters=30)
+
+
+def test_iterate_parity_row_classes(tmp_path):
+    """Rows ordered by length (long rows first): each workgroup's rows stay in
+    one length class, and the iterates match the oracle."""
+    q = synth.mixed_cone_scaled(seed=7, scale=0.02)
+    lens = np.diff(q.A.indptr)
+    order = np.argsort(-lens, kind="stable")
+    p = Problem(n=q.n, m=q.m, A=q.A[order].tocsr(), b=q.b[order], c=q.c, P=q.P, R=q.R, D=q.D,
+                cones=q.cones, name="mixed_cone_rows_by_length")
+    plens = np.diff(p.A.indptr)
+    cls = np.digitize(plens, [16.5, 64.5, 256.5, 1024.5])
+    assert len(set(cls)) >= 2
+    part = _partition_dump(p, tmp_path, grid_dim=24)
+    for w, r0, r1 in part[:, [0, 3, 4]]:
+        if r1 > r0:
+            assert len(set(cls[r0:r1])) == 1, (w, r0, r1)
+    trace_parity(p, grid_dim=24, iters=30)
+
+
 def test_iterate_parity_edge_cones():
     trace_parity(edge_cone_problem())
     trace_parity(edge_cone_problem(1), grid_dim=3)
