@@ -92,6 +92,42 @@ def bytes_model(prob, iters, inner_total, checks):
     return iters * per_iter + inner_bytes + check_bytes
 
 
+def footprint_bytes(prob):
+    """Device working set of one solve: A and A^T (values, int32 columns,
+    int64 row pointers), P, the dense factor R, and the iteration vectors
+    (about 17 of length n and 8 of length m, FP64)."""
+    nnz = prob.A.nnz
+    by = 2 * 12.0 * nnz + 8.0 * (prob.m + 1) + 8.0 * (prob.n + 1)
+    if prob.P is not None:
+        by += 12.0 * prob.P.nnz + 8.0 * (prob.n + 1)
+    if prob.R is not None:
+        by += 8.0 * prob.R.size
+    return by + 8.0 * (17 * prob.n + 8 * prob.m)
+
+
+def same_footprint_context(prob, s_per_iter, reps=20):
+    """Per-iteration time and the bandwidth of a plain device copy whose
+    source and destination together span the solve's working set: for a
+    cache-resident instance this, not the 8 TB/s HBM peak, is what a
+    bandwidth-bound kernel of the same footprint could reach."""
+    import torch
+    fb = footprint_bytes(prob)
+    half = max(int(fb // 16), 1)             # FP64 elements in each of src and dst
+    src = torch.ones(half, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return {"us_per_iteration": 1e6 * s_per_iter, "footprint_bytes": fb,
+            "same_footprint_copy_GBs": 2.0 * 8.0 * half / t / 1e9}
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The oracle as it stands, single thread, on the first outer iterations
     of the same instance; iterations/s."""
@@ -417,6 +453,7 @@ def main():
                      "launch": [grid, runs[-1]["block_dim"]],
                      "algorithmic_bytes_per_iteration": alg_bytes / iters},
     }
+    out["context"] = same_footprint_context(prob, ksum / iters)
     if not args.no_variants and args.workload == "mixed_cone":
         wall1 = wall / args.steps
         out["variants"] = {"fp32_bulk": fp32_variant(prob, args, wall1, last)}
