@@ -44,6 +44,8 @@ namespace pdhcg {
 constexpr int BLOCK = 512;
 constexpr int NWAVE = BLOCK / 64;
 
+constexpr int ITEM_CACHE = 256;   // cone items per kind cached in LDS
+
 struct Lds {
   double red[16][NWAVE];
   double scal[SL_COUNT];
@@ -52,6 +54,13 @@ struct Lds {
   double hw[NWAVE][RMAX];   // per-wave R^ u accumulators (single-workgroup teams)
   double hu[RMAX];       // R^ u of the current inner iterate
   double hs[RMAX];       // R^ s, s = u - u_prev (one-sync inner step)
+  // this workgroup's cone-item descriptors, copied once per launch when they
+  // fit (read by every projection pass)
+  int wst[ITEM_CACHE], wdim[ITEM_CACHE];
+  unsigned char wtype[ITEM_CACHE], weu[ITEM_CACHE];
+  int lst[ITEM_CACHE];
+  unsigned char ltype[ITEM_CACHE], leu[ITEM_CACHE];
+  double lal[ITEM_CACHE];
   Ctl C;
   int flag;
   int done;
@@ -516,7 +525,60 @@ struct StepSrc {            // u - alpha g / d
 // of the workgroup goes to wave k % NWAVE)
 struct Items {
   int w0, w1, l0, l1, lg;
+  const Lds* cache_w = nullptr;   // LDS copies of the wave-item / lane-item
+  const Lds* cache_l = nullptr;   // descriptors, or null: read them from P
 };
+
+__device__ __forceinline__ long wi_start(const DevProblem& P, const Items& I, int it) {
+  return I.cache_w ? I.cache_w->wst[it - I.w0] : P.wave_start[it];
+}
+__device__ __forceinline__ int wi_dim(const DevProblem& P, const Items& I, int it) {
+  return I.cache_w ? I.cache_w->wdim[it - I.w0] : P.wave_dim[it];
+}
+__device__ __forceinline__ int wi_type(const DevProblem& P, const Items& I, int it) {
+  return I.cache_w ? I.cache_w->wtype[it - I.w0] : P.wave_type[it];
+}
+__device__ __forceinline__ bool wi_euclid(const DevProblem& P, const Items& I, int it) {
+  return I.cache_w ? I.cache_w->weu[it - I.w0] != 0 : P.wave_euclid[it] != 0;
+}
+__device__ __forceinline__ long li_start(const DevProblem& P, const Items& I, int it) {
+  return I.cache_l ? I.cache_l->lst[it - I.l0] : P.lane_start[it];
+}
+__device__ __forceinline__ int li_type(const DevProblem& P, const Items& I, int it) {
+  return I.cache_l ? I.cache_l->ltype[it - I.l0] : P.lane_type[it];
+}
+__device__ __forceinline__ bool li_euclid(const DevProblem& P, const Items& I, int it) {
+  return I.cache_l ? I.cache_l->leu[it - I.l0] != 0 : P.lane_euclid[it] != 0;
+}
+__device__ __forceinline__ double li_alpha(const DevProblem& P, const Items& I, int it) {
+  return I.cache_l ? I.cache_l->lal[it - I.l0] : P.lane_alpha[it];
+}
+
+// copy the workgroup's item descriptors into L when they fit; returns the
+// Items with the cache pointers set
+__device__ Items cache_items(const DevProblem& P, Items I, Lds& L) {
+  const int nw = I.w1 - I.w0, nl = I.l1 - I.l0;
+  if (nw > 0 && nw <= ITEM_CACHE) {
+    for (int k = threadIdx.x; k < nw; k += BLOCK) {
+      L.wst[k] = P.wave_start[I.w0 + k];
+      L.wdim[k] = P.wave_dim[I.w0 + k];
+      L.wtype[k] = P.wave_type[I.w0 + k];
+      L.weu[k] = P.wave_euclid[I.w0 + k];
+    }
+    I.cache_w = &L;
+  }
+  if (nl > 0 && nl <= ITEM_CACHE) {
+    for (int k = threadIdx.x; k < nl; k += BLOCK) {
+      L.lst[k] = P.lane_start[I.l0 + k];
+      L.ltype[k] = P.lane_type[I.l0 + k];
+      L.leu[k] = P.lane_euclid[I.l0 + k];
+      L.lal[k] = P.lane_alpha[I.l0 + k];
+    }
+    I.cache_l = &L;
+  }
+  __syncthreads();
+  return I;
+}
 
 // warm (nullable): previous roots of the root-finding projections, one per
 // item (wave items first, then lane items), read as starting points and
@@ -527,11 +589,11 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;                       // groups per wave
   for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
-    const long st = P.wave_start[it];
+    const long st = wi_start(P, I, it);
     auto src = make(st);
-    const bool eu = force_euclid || P.wave_euclid[it];
+    const bool eu = force_euclid || wi_euclid(P, I, it);
     const unsigned long long t0 = ptw ? wall_clock64() : 0ull;
-    project_wave_item(P.wave_type[it], P.wave_dim[it], eu, src,
+    project_wave_item(wi_type(P, I, it), wi_dim(P, I, it), eu, src,
                       [&](int j, double v) { dst[st + j] = v; }, warm ? warm + it : nullptr, I.lg);
     if (ptw && threadIdx.x == 0) {
       ptw[0] += wall_clock64() - t0;
@@ -541,16 +603,16 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
   for (int kb = 0; I.l0 + kb < I.l1; kb += BLOCK) {
     const int it = I.l0 + kb + wv + NWAVE * lane;
     if (it < I.l1) {
-      const long st = P.lane_start[it];
+      const long st = li_start(P, I, it);
       auto src = make(st);
-      const bool eu = force_euclid || P.lane_euclid[it];
+      const bool eu = force_euclid || li_euclid(P, I, it);
       const double r0 = src.r(0), r1 = src.r(1), r2 = src.r(2);
       double m0 = 1.0, m1 = 1.0, m2 = 1.0;
       if (!eu) { m0 = src.m(0); m1 = src.m(1); m2 = src.m(2); }
       double o[3];
       double* w = warm ? warm + P.n_wave + it : nullptr;
-      if (P.lane_type[it] == PDHCG_CONE_EXP) project_exp(r0, r1, r2, m0, m1, m2, o, w);
-      else project_pow(r0, r1, r2, P.lane_alpha[it], m0, m1, m2, o, w);
+      if (li_type(P, I, it) == PDHCG_CONE_EXP) project_exp(r0, r1, r2, m0, m1, m2, o, w);
+      else project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, o, w);
       dst[st] = o[0];
       dst[st + 1] = o[1];
       dst[st + 2] = o[2];
@@ -569,8 +631,8 @@ __device__ __forceinline__ void for_item_coords(const DevProblem& P, const Items
   for (int base = I.w0 + wv * gpw; base < I.w1; base += NWAVE * gpw) {
     const int it = base + lane / I.lg;
     const bool ok = it < I.w1;
-    const long st = ok ? P.wave_start[it] : 0;
-    const int dim = ok ? P.wave_dim[it] : 0;
+    const long st = ok ? wi_start(P, I, it) : 0;
+    const int dim = ok ? wi_dim(P, I, it) : 0;
     int maxd = dim;                                  // longest block of the wave
     for (int o = 32; o >= 1; o >>= 1) maxd = max(maxd, __shfl_xor(maxd, o, 64));
     for (int jb = 0; jb < maxd; jb += I.lg) {
@@ -581,7 +643,7 @@ __device__ __forceinline__ void for_item_coords(const DevProblem& P, const Items
   for (int kb = 0; I.l0 + kb < I.l1; kb += BLOCK) {
     const int it = I.l0 + kb + wv + NWAVE * lane;
     const bool act = it < I.l1;
-    const long st = act ? P.lane_start[it] : 0;
+    const long st = act ? li_start(P, I, it) : 0;
     for (int j = 0; j < 3; ++j) f(st + j, act);
   }
 }
@@ -622,7 +684,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   const TraceBufs& TB = *A.T;
   double* part = V.partials;
   const long c0 = own.c0, c1 = own.c1, r0 = own.r0, r1 = own.r1;
-  const Items& IT = own.it;
+  const Items IT = CONES ? cache_items(P, own.it, L) : own.it;
   // CONES = false: the variant for problems whose blocks are all FREE or R+,
   // compiled without the cone projections (far fewer registers)
   const bool has_items = CONES && ((IT.w1 > IT.w0) || (IT.l1 > IT.l0));
