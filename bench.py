@@ -35,7 +35,7 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "mixed_cone", "grid": 256, "iterations": 448,
-    "sources_sha256": "c3257e95e68e5f40360bbe4432a61627558f1cf091436d6ee26180f7aa722c9e",
+    "sources_sha256": "8070a00051cacec71bc9a330cd9f5db34e23d24c6ee7fa99dbfc99d87944ffb6",
     "bytes_per_launch": 12267678.0625 * 1024 * 1.99966 + 14498875.375 * 1024 * 1.0,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")

@@ -21,6 +21,12 @@
 //   P3  (general Q, repeated) g = Q u + c + (u - v)/tau, BB sums.    | barrier
 //   P4  projected step with alpha = <s,Js>/<s,dg>; stop when the Euclidean
 //       step norm <= eps_in (eq. current-inner-step-stop).           | barrier
+//       With P diagonal or absent (grids), P3 and P4 share one barrier:
+//       the BB sums of the step just taken are reduced with it, since the
+//       gradient is affine in u (see the inner loop).
+//   R u (dense factor) partials: grids form them after each coordinate pass
+//   from the stored iterate (one wave per factor row); single-workgroup
+//   teams accumulate them inside the pass.
 //   P6  own rows: A w_x, w_y = y + sigma (b - (2 A w_x - A x)); on non-check
 //       iterations the Halpern update of x, y, A x is fused.          | barrier
 //   Check iterations (k = 0 of an epoch and every check_every evaluations):
