@@ -141,7 +141,9 @@ typedef struct {
     int32_t precision;            /* PDHCG_PREC_* (default FP64)              */
     int32_t trace_iters;          /* record the first k outer iterations      */
     int32_t block_dim;            /* 0 = auto                                 */
-    int32_t grid_dim;             /* 0 = auto                                 */
+    int32_t grid_dim;             /* 0 = auto; 1 runs the single-workgroup
+                                     variant, whose arithmetic is that of a
+                                     batch solve of the same instance        */
     int32_t lanes_at;             /* lanes per row of A^T / P (0 = auto)      */
     int32_t lanes_a;              /* lanes per row of A (0 = auto)            */
     int32_t host_poll;            /* outer iterations per launch (default 512)*/
