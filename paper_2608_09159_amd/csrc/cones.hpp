@@ -257,7 +257,7 @@ struct RsocView {
 // blocks (all reductions stay inside the group).  warm (nullable)
 // holds the previous root of this block and receives the new one.
 template <class Src, class Sink>
-__device__ __noinline__ void project_wave_item(int type, int dim, bool euclid, const Src& src, Sink sink,
+__device__ __noinline__ void project_wave_item(int type, int dim, bool euclid, Src src, Sink sink,
                                                double* warm, int Lg) {
   const int lane = threadIdx.x & (Lg - 1);
   if (type == 2) {
@@ -573,8 +573,8 @@ __device__ void note_cone_failure(int type, double a, double b, double c, double
   }
 }
 
-__device__ __noinline__ void project_exp(double r0, double s0, double t0, double mr, double ms, double mt,
-                            double out[3], double* warm) {
+__device__ __forceinline__ void project_exp_body(double r0, double s0, double t0, double mr, double ms,
+                                                 double mt, double out[3], double* warm) {
   if (exp_in_cone(r0, s0, t0)) { out[0] = r0; out[1] = s0; out[2] = t0; return; }
   if (exp_in_dual(-mr * r0, -ms * s0, -mt * t0)) { out[0] = out[1] = out[2] = 0.0; return; }
   if (r0 <= 0.0 && s0 <= 0.0) { out[0] = r0; out[1] = 0.0; out[2] = fmax(t0, 0.0); return; }
@@ -650,8 +650,8 @@ __device__ __forceinline__ double pow_qroot(double s, double c) {
   return s >= 0.0 ? 0.5 * (s + d) : 2.0 * c / (d - s);
 }
 
-__device__ __noinline__ void project_pow(double x, double y, double z, double al, double mx, double my,
-                            double mz, double out[3], double* warm) {
+__device__ __forceinline__ void project_pow_body(double x, double y, double z, double al, double mx, double my,
+                                                 double mz, double out[3], double* warm) {
   if (z == 0.0) { out[0] = fmax(x, 0.0); out[1] = fmax(y, 0.0); out[2] = 0.0; return; }
   if (x >= 0.0 && y >= 0.0 && pow(x, al) * pow(y, 1.0 - al) >= fabs(z)) {
     out[0] = x; out[1] = y; out[2] = z; return;
@@ -696,6 +696,27 @@ __device__ __noinline__ void project_pow(double x, double y, double z, double al
   out[0] = pow_qroot(x, cx * w);
   out[1] = pow_qroot(y, cy * w);
   out[2] = copysign(rho, z);
+}
+
+// Out-of-line entry points (one copy of each root-finder in the code, kept
+// apart from the register allocation of the solver loop); the projected
+// point comes back in registers, not through the caller's stack.
+struct Trip {
+  double a, b, c;
+};
+
+__device__ __noinline__ Trip project_exp(double r0, double s0, double t0, double mr, double ms, double mt,
+                                         double* warm) {
+  double o[3];
+  project_exp_body(r0, s0, t0, mr, ms, mt, o, warm);
+  return Trip{o[0], o[1], o[2]};
+}
+
+__device__ __noinline__ Trip project_pow(double x, double y, double z, double al, double mx, double my,
+                                         double mz, double* warm) {
+  double o[3];
+  project_pow_body(x, y, z, al, mx, my, mz, o, warm);
+  return Trip{o[0], o[1], o[2]};
 }
 
 }  // namespace pdhcg

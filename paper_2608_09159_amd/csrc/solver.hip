@@ -600,7 +600,7 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
     const bool eu = force_euclid || wi_euclid(P, I, it);
     const unsigned long long t0 = ptw ? wall_clock64() : 0ull;
     project_wave_item(wi_type(P, I, it), wi_dim(P, I, it), eu, src,
-                      [&](int j, double v) { dst[st + j] = v; }, warm ? warm + it : nullptr, I.lg);
+                      [dst, st](int j, double v) { dst[st + j] = v; }, warm ? warm + it : nullptr, I.lg);
     if (ptw && threadIdx.x == 0) {
       ptw[0] += wall_clock64() - t0;
       ptw[1] += 1;
@@ -615,13 +615,12 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
       const double r0 = src.r(0), r1 = src.r(1), r2 = src.r(2);
       double m0 = 1.0, m1 = 1.0, m2 = 1.0;
       if (!eu) { m0 = src.m(0); m1 = src.m(1); m2 = src.m(2); }
-      double o[3];
       double* w = warm ? warm + P.n_wave + it : nullptr;
-      if (li_type(P, I, it) == PDHCG_CONE_EXP) project_exp(r0, r1, r2, m0, m1, m2, o, w);
-      else project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, o, w);
-      dst[st] = o[0];
-      dst[st + 1] = o[1];
-      dst[st + 2] = o[2];
+      const Trip o = li_type(P, I, it) == PDHCG_CONE_EXP ? project_exp(r0, r1, r2, m0, m1, m2, w)
+                                                         : project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, w);
+      dst[st] = o.a;
+      dst[st + 1] = o.b;
+      dst[st + 2] = o.c;
     }
   }
   __syncthreads();
