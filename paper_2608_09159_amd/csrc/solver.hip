@@ -51,6 +51,7 @@ constexpr int BLOCK = 512;
 constexpr int NWAVE = BLOCK / 64;
 
 constexpr int ITEM_CACHE = 256;   // cone items per kind cached in LDS
+constexpr int ZCAP = 1024;        // coordinates whose projection inputs/outputs can stage in LDS
 
 struct Lds {
   double red[16][NWAVE];
@@ -67,6 +68,9 @@ struct Lds {
   int lst[ITEM_CACHE];
   unsigned char ltype[ITEM_CACHE], leu[ITEM_CACHE];
   double lal[ITEM_CACHE];
+  // the inner step's cone-coordinate gradient and projected point, indexed
+  // from the workgroup's first coordinate (when it owns at most ZCAP)
+  double gl[ZCAP], zl[ZCAP];
   Ctl C;
   int flag;
   int done;
@@ -515,13 +519,14 @@ struct NegSrc {
   __device__ double m(int j) const { return 1.0; }
 };
 
-struct StepSrc {            // u - alpha g / d
+struct StepSrc {            // u - alpha g / d  (g indexed from gb)
   const double* u;
   const double* g;
   MetricQ M;
   double alpha;
   long st;
-  __device__ double r(int j) const { return u[st + j] - alpha * g[st + j] / M(st + j); }
+  long gb;
+  __device__ double r(int j) const { return u[st + j] - alpha * g[st + j - gb] / M(st + j); }
   __device__ double m(int j) const { return M(st + j); }
 };
 
@@ -591,7 +596,7 @@ __device__ Items cache_items(const DevProblem& P, Items I, Lds& L) {
 // overwritten with the new roots
 template <class MakeSrc>
 __device__ __forceinline__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
-                              double* dst, double* warm, unsigned long long* ptw = nullptr) {
+                              double* dst, double* warm, unsigned long long* ptw = nullptr, long dbase = 0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;                       // groups per wave
   for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
@@ -600,7 +605,8 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
     const bool eu = force_euclid || wi_euclid(P, I, it);
     const unsigned long long t0 = ptw ? wall_clock64() : 0ull;
     project_wave_item(wi_type(P, I, it), wi_dim(P, I, it), eu, src,
-                      [dst, st](int j, double v) { dst[st + j] = v; }, warm ? warm + it : nullptr, I.lg);
+                      [dst, st, dbase](int j, double v) { dst[st + j - dbase] = v; }, warm ? warm + it : nullptr,
+                      I.lg);
     if (ptw && threadIdx.x == 0) {
       ptw[0] += wall_clock64() - t0;
       ptw[1] += 1;
@@ -618,9 +624,9 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
       double* w = warm ? warm + P.n_wave + it : nullptr;
       const Trip o = li_type(P, I, it) == PDHCG_CONE_EXP ? project_exp(r0, r1, r2, m0, m1, m2, w)
                                                          : project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, w);
-      dst[st] = o.a;
-      dst[st + 1] = o.b;
-      dst[st + 2] = o.c;
+      dst[st - dbase] = o.a;
+      dst[st + 1 - dbase] = o.b;
+      dst[st + 2 - dbase] = o.c;
     }
   }
   __syncthreads();
@@ -724,6 +730,14 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   // nothing back
   constexpr bool SOLO = std::is_same<Team, SoloTeam>::value;
   const bool fuse = !SOLO && !P.q_diag && (P.p_diag || !P.P_ptr);
+  // inner-step staging of the cone coordinates' gradient (one-sync step
+  // only) and projected point: LDS when the workgroup owns at most ZCAP
+  // coordinates, else the global g and zb
+  const bool zlds = (own.c1 - own.c0) <= ZCAP;
+  double* const gst = (fuse && zlds) ? L.gl : V.g;
+  const long gsb = (fuse && zlds) ? own.c0 : 0;
+  double* const zst = zlds ? L.zl : V.zb;
+  const long zsb = zlds ? own.c0 : 0;
   // the R v partial of this workgroup after a coordinate pass that wrote v
   // (and R (v - vp) for the one-sync inner step)
   auto hw_finish = [&](const auto& R, const double* v, const double* vp) {
@@ -961,7 +975,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
               const double ru = r_dot(RB, r, i, L.ht);
               const double pu = P.p_diag ? P.Pd[i] * ui : 0.0;
               gi = pu + ru + P.c[i] + (ui - V.v[i]) / tau;
-              if (!el) V.g[i] = gi;
+              if (!el) gst[i - gsb] = gi;
             } else {
               gi = V.g[i];
             }
@@ -985,12 +999,12 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         if (has_items) {
           if (fuse) __syncthreads();
           PROJ(project_items(P, IT, !jac,
-                             [&](long st) { return StepSrc{V.u, V.g, Mq, alpha, st}; }, V.zb, V.warm,
-                             prof ? &L.pt[PT_WCALL] : nullptr));
+                             [&](long st) { return StepSrc{V.u, gst, Mq, alpha, st, gsb}; }, zst, V.warm,
+                             prof ? &L.pt[PT_WCALL] : nullptr, zsb));
           for_item_coords(P, IT, [&](long i, bool act) {
             double un = 0.0;
             if (act) {
-              un = V.zb[i];
+              un = zst[i - zsb];
               const double ui = V.u[i];
               const double si = un - ui;
               acc[0] += si * si;
