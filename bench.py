@@ -29,14 +29,14 @@ HBM_PEAK_GBS = 8000.0
 BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 # HBM traffic of one solve_kernel launch on the default workload, from two
-# rocprofv3 counter runs (FETCH_SIZE x 1.99968, WRITE_SIZE x 1.0: the factors
+# rocprofv3 counter runs (FETCH_SIZE x 1.99967, WRITE_SIZE x 1.0: the factors
 # that make a 256 MiB device copy read and write 256 MiB).  Valid only for the
 # kernel sources whose hash is recorded, at the recorded grid; otherwise the
 # bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "mixed_cone", "grid": 256, "iterations": 448,
-    "sources_sha256": "0e4f2247ab622c01f5c7a0b0065f9bf938872ac33ecbfd918db0354908512429",
-    "bytes_per_launch": 10623447.1875 * 1024 * 1.99968 + 11169043.125 * 1024 * 1.0,
+    "sources_sha256": "4950cf1b8289aae72b87fceaee366390725576d3e7155baea26b108f6ac0281d",
+    "bytes_per_launch": 10552558.0 * 1024 * 1.99967 + 11241005.4375 * 1024 * 1.0,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
