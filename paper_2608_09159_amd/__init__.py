@@ -15,6 +15,9 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
     Handle.trace(count) -> dict               (pdhcg_get_trace)
     Handle.scaling() -> dict                  (pdhcg_get_scaling)
     Handle.free()                             (pdhcg_free)
+    MLP(dims, max_batch).forward / .train_step / .set_params / .get_params /
+        .grads / .free                        (pdhcg_mlp_*: the warm-start
+                                               network's BF16 matrix-core kernels)
 
 ``problem`` is any object with the fields of ``instances.Problem``
 (n, m, A as scipy CSR, b, c, optional P / R / D, cones as
