@@ -11,6 +11,8 @@ Readings where the paper is silent:
   sqrt(max_i |A_li|), Pock-Chambolle row factor sqrt(sum_i |A_li|^alpha)
   (the Pock-Chambolle pairing of exponents alpha / 2 - alpha);
 * a zero row or column gets the factor 1;
+* the Pock-Chambolle sums run over the stored nonzeros of A~, so an exponent
+  of zero (alpha = 0 for rows, alpha = 2 for columns) counts them;
 * order: Ruiz passes, then Pock-Chambolle, then bound-objective;
 * bound-objective constants: nu_b = ||b~|| + 1, nu_c = ||c~|| + 1,
   b^ = b~/nu_b, c^ = c~/nu_c and Q^ = (nu_b/nu_c) Q~, which keeps the
@@ -22,9 +24,13 @@ With x~ = S_x x, A~ = S_y A S_x^-1, Q~ = S_x^-1 Q S_x^-1, c~ = S_x^-1 c,
 b~ = S_y b; an original solution is recovered as x = nu_b S_x^-1 x^,
 y = nu_c S_y y^.
 
-Pins (tests/test_oracle_solver.py): unscale(scale(.)) is the identity, the
-unscaled KKT residuals of a solve do not depend on the scaling, and after the
-Ruiz passes every row and column infinity-norm is close to one.
+Pins: hand-derived worked examples of one and two Ruiz passes, of a
+Pock-Chambolle pass with alpha = 1 and alpha = 2, of Ruiz followed by
+Pock-Chambolle and of the bound-objective constants
+(tests/test_oracle_pins.py); unscale(scale(.)) is the identity, the unscaled
+KKT residuals of a solve do not depend on the scaling, and after the Ruiz
+passes every row and column infinity-norm is close to one
+(tests/test_oracle_solver.py).
 """
 from __future__ import annotations
 
@@ -69,6 +75,14 @@ def _apply(A, row, col):
     return sp.diags(1.0 / row) @ A @ sp.diags(1.0 / col)
 
 
+def _abs_power_sums(A, e):
+    """(row sums, column sums) of |A_li|^e over the nonzeros of A."""
+    B = abs(A).tocsr()
+    B.eliminate_zeros()
+    B.data = B.data ** e
+    return (np.asarray(B.sum(axis=1)).ravel(), np.asarray(B.sum(axis=0)).ravel())
+
+
 def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
                   bound_objective=True, enabled=True):
     A = sp.csr_matrix(prob.A, dtype=float, copy=True)
@@ -89,9 +103,8 @@ def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
             Sy = Sy / row
             Sx = Sx * col
         if pock_chambolle:
-            absA = abs(A)
-            col = np.sqrt(np.asarray(absA.power(2.0 - pc_alpha).sum(axis=0)).ravel())
-            row = np.sqrt(np.asarray(absA.power(pc_alpha).sum(axis=1)).ravel())
+            col = np.sqrt(_abs_power_sums(A, 2.0 - pc_alpha)[1])
+            row = np.sqrt(_abs_power_sums(A, pc_alpha)[0])
             for st, d in blocks:          # eq. cone-preserving-scaling (PC: RMS)
                 col[st:st + d] = np.sqrt(np.mean(col[st:st + d] ** 2))
             col[col == 0] = 1.0

@@ -315,7 +315,8 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
       std::fill(col.begin(), col.end(), 0.0);
       for (int64_t l = 0; l < m; ++l)
         for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
-          double a = std::fabs(A.val[k]);
+          const double a = std::fabs(A.val[k]);
+          if (a == 0.0) continue;   // sums over the nonzeros (an exponent 0 counts them)
           row[l] += std::pow(a, al);
           col[A.col[k]] += std::pow(a, 2.0 - al);
         }

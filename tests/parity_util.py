@@ -47,7 +47,6 @@ def assert_trace_matches(name, tr, o):
     iteration (the inner-step counts, check and restart decisions exactly)."""
     prob_name = name
     assert tr["count"] == len(o.trace), (tr["count"], len(o.trace))
-    last = tr["count"] - 1
     for k, ot in enumerate(o.trace):
         for key in ("x", "y", "wx", "wy"):
             err = _rel(tr[key][k], ot[key])
@@ -55,11 +54,10 @@ def assert_trace_matches(name, tr, o):
         for key in ("tau", "sigma", "omega", "eps_in"):
             assert tr[key][k] == pytest.approx(ot[key], rel=ITER_TOL), (prob_name, k, key)
         assert tr["inner"][k] == ot["inner"], (prob_name, k, "inner")
-        if k < last or o.status == "OPTIMAL":
-            assert bool(tr["check"][k]) == bool(ot["check"]), (prob_name, k, "check")
-            assert bool(tr["restart"][k]) == bool(ot["restart"]), (prob_name, k, "restart")
-            if ot["check"]:
-                assert tr["E"][k] == pytest.approx(ot["E"], rel=1e-9, abs=1e-300)
+        assert bool(tr["check"][k]) == bool(ot["check"]), (prob_name, k, "check")
+        assert bool(tr["restart"][k]) == bool(ot["restart"]), (prob_name, k, "restart")
+        if ot["check"]:
+            assert tr["E"][k] == pytest.approx(ot["E"], rel=1e-9, abs=1e-300)
 
 
 def final_parity(prob, **kw):
