@@ -256,7 +256,27 @@ int pdhcg_get_scaling(void* h, int32_t inst, double* Sx, double* Sy,
  * after the solve has returned.                                            */
 int pdhcg_last_cone_failure(double* rec, int64_t* count);
 
-/* Release every host and device resource of h (NULL is a no-op).          */
+/* Diagnostic (not on the solve path): project `count` blocks of one cone
+ * type with the same device routines the solver uses, so they can be
+ * compared with an independent implementation.  Appendix C gives the
+ * projections: the closed forms onto R+, SOC and RSOC, the root of h_M for
+ * EXP and the bisection of Prop. power-cone-bisection for POW, all in the
+ * diagonal metric of eq. metric-block-projection,
+ *     Pi^M_K(r) = argmin_{u in K} 1/2 ||u - r||_M^2,  M = diag(metric).
+ * type: PDHCG_CONE_*; dim: coordinates per block (RSOC >= 2, EXP/POW 3).
+ * r, out: count*dim doubles, block after block, in the coordinate order of
+ * the cone list (host pointers, caller-owned).  metric: count*dim positive
+ * entries, or NULL for the Euclidean projection; a block whose metric is
+ * constant takes the Euclidean formula, as in the solver.  alpha: count
+ * exponents in (0, 1), POW only (nullable otherwise).  Root-finding failures
+ * give NaN in out (see pdhcg_last_cone_failure).  Runs on the null stream
+ * and returns when out is filled.  Errors: PDHCG_E_ARG (bad type, sizes,
+ * null pointers, metric <= 0), PDHCG_E_CONE (dim, alpha), PDHCG_E_MEM,
+ * PDHCG_E_HIP.                                                            */
+int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha,
+                        const double* r, const double* metric, double* out);
+
+/* Release every host and device resource of h (NULL is a no-op).          *//* Release every host and device resource of h (NULL is a no-op).          */
 void pdhcg_free(void* h);
 
 /* Static description of an error code or status.                          */

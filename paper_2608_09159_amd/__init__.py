@@ -15,6 +15,7 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
     Handle.trace(count) -> dict               (pdhcg_get_trace)
     Handle.scaling() -> dict                  (pdhcg_get_scaling)
     Handle.free()                             (pdhcg_free)
+    project_cones(kind, r, metric, alpha)     (pdhcg_project_cones, diagnostic)
     MLP(dims, max_batch).forward / .train_step / .set_params / .get_params /
         .grads / .free                        (pdhcg_mlp_*: the warm-start
                                                network's BF16 matrix-core kernels)
@@ -95,7 +96,7 @@ _LIB = None
 
 EXPORTS = ("pdhcg_default_settings", "pdhcg_setup", "pdhcg_solve", "pdhcg_solve_batch",
            "pdhcg_get_trace", "pdhcg_get_scaling", "pdhcg_free", "pdhcg_strerror",
-           "pdhcg_version", "pdhcg_last_cone_failure", "pdhcg_mlp_create", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
+           "pdhcg_version", "pdhcg_last_cone_failure", "pdhcg_project_cones", "pdhcg_mlp_create", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
            "pdhcg_mlp_forward", "pdhcg_mlp_train_step", "pdhcg_mlp_get_grads", "pdhcg_mlp_free")
 
 
@@ -139,6 +140,7 @@ def load(path=None):
     lib.pdhcg_strerror.restype = C.c_char_p
     lib.pdhcg_version.restype = C.c_char_p
     lib.pdhcg_last_cone_failure.argtypes = [_dp, C.POINTER(C.c_int64)]
+    lib.pdhcg_project_cones.argtypes = [C.c_int32, C.c_int32, C.c_int64, _dp, _dp, _dp, _dp]
     _fp = C.POINTER(C.c_float)
     lib.pdhcg_mlp_create.argtypes = [C.c_int32, _i32p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.pdhcg_mlp_set_params.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
@@ -311,6 +313,28 @@ def last_cone_failure():
     _check(load().pdhcg_last_cone_failure(_ptr(rec, C.c_double), C.byref(cnt)),
            "pdhcg_last_cone_failure")
     return int(cnt.value), rec
+
+
+def project_cones(kind, r, metric=None, alpha=None):
+    """pdhcg_project_cones: r is a (count, dim) array of blocks of one cone
+    type (name or code); metric the same shape or None; alpha (count,) for
+    POW.  Returns the projected blocks."""
+    code = CONE_CODES[kind] if isinstance(kind, str) else int(kind)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    if r.ndim != 2:
+        raise ValueError("r must be (count, dim)")
+    count, dim = r.shape
+    m = None if metric is None else np.ascontiguousarray(metric, dtype=np.float64)
+    if m is not None and m.shape != r.shape:
+        raise ValueError("metric must have the shape of r")
+    a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+    if a is not None and a.shape != (count,):
+        raise ValueError("alpha must have one entry per block")
+    out = np.empty_like(r)
+    _check(load().pdhcg_project_cones(code, dim, count, _ptr(a, C.c_double), _ptr(r, C.c_double),
+                                      _ptr(m, C.c_double), _ptr(out, C.c_double)),
+           "pdhcg_project_cones")
+    return out
 
 
 class BatchHandle(Handle):

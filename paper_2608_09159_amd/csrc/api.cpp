@@ -275,7 +275,7 @@ int upload_instance(Handle* h, Instance* I) {
 
   // launch geometry
   int maxg = 1;
-  HIPCHK(max_coop_grid(&maxg));
+  HIPCHK(max_resident_grid(&maxg));
   int G = h->s.grid_dim;
   if (G <= 0) {
     long work = std::max<long>(std::max<long>(n, m), 1);
@@ -1408,6 +1408,51 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count) {
   if (cnt == 0)
     for (int i = 0; i < 8; ++i) rec[i] = 0.0;
   return PDHCG_OK;
+}
+
+int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha, const double* r,
+                        const double* metric, double* out) {
+  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;
+  if ((type == PDHCG_CONE_RSOC && dim < 2) ||
+      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) && dim != 3))
+    return PDHCG_E_CONE;
+  if (count == 0) return PDHCG_OK;
+  if (!r || !out || (type == PDHCG_CONE_POW && !alpha)) return PDHCG_E_ARG;
+  const size_t len = (size_t)count * (size_t)dim;
+  std::vector<unsigned char> eu((size_t)count, 1);
+  if (metric) {
+    for (size_t i = 0; i < len; ++i)
+      if (!(metric[i] > 0.0) || !std::isfinite(metric[i])) return PDHCG_E_ARG;
+    // a metric that is constant on a block takes the Euclidean formula, as in
+    // the solver (Pi^{cI} = Pi^I)
+    for (int64_t b = 0; b < count; ++b) {
+      const double* mb = metric + (size_t)b * dim;
+      bool c = true;
+      for (int j = 1; j < dim; ++j) c = c && (mb[j] == mb[0]);
+      eu[(size_t)b] = c ? 1 : 0;
+    }
+  }
+  if (type == PDHCG_CONE_POW)
+    for (int64_t b = 0; b < count; ++b)
+      if (!(alpha[b] > 0.0 && alpha[b] < 1.0)) return PDHCG_E_CONE;
+  DevBuf B;
+  double* d_r = B.alloc<double>(len);
+  double* d_o = B.alloc<double>(len);
+  double* d_m = metric ? B.alloc<double>(len) : nullptr;
+  double* d_a = type == PDHCG_CONE_POW ? B.alloc<double>((size_t)count) : nullptr;
+  unsigned char* d_e = B.alloc<unsigned char>((size_t)count);
+  if (B.err != hipSuccess) {
+    B.release();
+    return PDHCG_E_MEM;
+  }
+  hipError_t e = hipMemcpy(d_r, r, len * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess && d_m) e = hipMemcpy(d_m, metric, len * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess && d_a) e = hipMemcpy(d_a, alpha, (size_t)count * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_e, eu.data(), (size_t)count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_project(type, dim, (long)count, d_a, d_r, d_m, d_e, d_o, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, d_o, len * sizeof(double), hipMemcpyDeviceToHost);
+  B.release();
+  return e == hipSuccess ? PDHCG_OK : PDHCG_E_HIP;
 }
 
 int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {

@@ -1542,19 +1542,74 @@ __global__ __launch_bounds__(BLOCK) void batch_gather_kernel(const InstDesc* des
 }
 
 // ---------------------------------------------------------------------------
+// diagnostic: a batch of blocks of one cone type projected by the solver's
+// own projection routines (wave items for SOC/RSOC with a group of lg lanes
+// per block, one lane per EXP/POW block, elementwise FREE/R+); blocks are
+// stored one after another, dim coordinates each
+// ---------------------------------------------------------------------------
+struct ArrSrc {
+  const double* rv;
+  const double* mv;   // null: unit metric
+  long st;
+  __device__ double r(int j) const { return rv[st + j]; }
+  __device__ double m(int j) const { return mv ? mv[st + j] : 1.0; }
+};
+
+__global__ __launch_bounds__(BLOCK) void project_kernel(int type, int dim, long count, const double* alpha,
+                                                        const double* r, const double* m,
+                                                        const unsigned char* euclid, double* out, int lg) {
+  const long gtid = (long)blockIdx.x * BLOCK + threadIdx.x;
+  const long nthr = (long)gridDim.x * BLOCK;
+  if (type == PDHCG_CONE_SOC || type == PDHCG_CONE_RSOC) {
+    const long ngroups = nthr / lg;
+    for (long b = gtid / lg; b < count; b += ngroups) {
+      const long st = b * (long)dim;
+      project_wave_item(type, dim, euclid[b] != 0, ArrSrc{r, m, st},
+                        [out, st](int j, double v) { out[st + j] = v; }, nullptr, lg);
+    }
+  } else if (type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) {
+    for (long b = gtid; b < count; b += nthr) {
+      const long st = 3 * b;
+      const bool eu = euclid[b] != 0;
+      const double m0 = eu ? 1.0 : m[st], m1 = eu ? 1.0 : m[st + 1], m2 = eu ? 1.0 : m[st + 2];
+      const Trip o = type == PDHCG_CONE_EXP ? project_exp(r[st], r[st + 1], r[st + 2], m0, m1, m2, nullptr)
+                                            : project_pow(r[st], r[st + 1], r[st + 2], alpha[b], m0, m1, m2,
+                                                          nullptr);
+      out[st] = o.a;
+      out[st + 1] = o.b;
+      out[st + 2] = o.c;
+    }
+  } else {
+    const uint8_t ct = type == PDHCG_CONE_FREE ? CT_FREE : CT_NONNEG;
+    for (long i = gtid; i < count * (long)dim; i += nthr) out[i] = elem_proj(ct, r[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
 int block_size() { return BLOCK; }
 
+// A plain launch: the grid barrier needs every workgroup resident at once,
+// so the launch is refused when the grid exceeds what the device holds
+// with this kernel's registers and LDS (the barrier's waits are bounded as
+// well, so a grid that cannot all be resident ends with PDHCG_ABORTED, not a
+// hang).
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream) {
   KArgs a = args;
   void* params[] = {&a};
   const void* k = fp32 ? (const void*)solve_kernel_f32
                        : (grid == 1 ? (const void*)solve_kernel_one : (const void*)solve_kernel);
-  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BLOCK), params, (size_t)args.lds_bytes, stream);
+  int dev = 0, ncu = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, BLOCK, (size_t)args.lds_bytes);
+  if (e != hipSuccess) return e;
+  if ((long)per * (long)ncu < (long)grid) return hipErrorCooperativeLaunchTooLarge;
+  return hipLaunchKernel(k, dim3(grid), dim3(BLOCK), params, (size_t)args.lds_bytes, stream);
 }
 
-hipError_t max_coop_grid(int* out) {
+hipError_t max_resident_grid(int* out) {
   int dev = 0, ncu = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1636,6 +1691,24 @@ hipError_t read_cone_failure(double rec[8], unsigned* count) {
   hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_cone_fail_count), sizeof(unsigned));
   if (e != hipSuccess) return e;
   return hipMemcpyFromSymbol(rec, HIP_SYMBOL(g_cone_fail), 8 * sizeof(double));
+}
+
+hipError_t launch_project(int type, int dim, long count, const double* alpha, const double* r,
+                          const double* m, const unsigned char* euclid, double* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int lg = 1;
+  long threads = count;
+  if (type == PDHCG_CONE_SOC || type == PDHCG_CONE_RSOC) {
+    // the group width the solver gives a block of this size
+    lg = dim <= 17 ? 16 : (dim <= 33 ? 32 : 64);
+    threads = count * lg;
+  } else if (type != PDHCG_CONE_EXP && type != PDHCG_CONE_POW) {
+    threads = count * (long)dim;
+  }
+  const long grid = std::max<long>(1, std::min<long>((threads + BLOCK - 1) / BLOCK, 4096));
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, type, dim, count, alpha, r, m,
+                     euclid, out, lg);
+  return hipGetLastError();
 }
 
 int batch_grid_limit(bool cones) {

