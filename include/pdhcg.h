@@ -276,7 +276,7 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count);
 int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha,
                         const double* r, const double* metric, double* out);
 
-/* Release every host and device resource of h (NULL is a no-op).          *//* Release every host and device resource of h (NULL is a no-op).          */
+/* Release every host and device resource of h (NULL is a no-op).          */
 void pdhcg_free(void* h);
 
 /* Static description of an error code or status.                          */

@@ -388,9 +388,10 @@ def _solve_avg(S: Setup, x0, y0):
             inner_tot += nin
             ktot += 1
             if len(trace) < st.trace_iters:
+                end = k + 1 == st.avg_epoch or ktot >= st.max_iter   # restart and check follow
                 trace.append(dict(x=x.copy(), y=y.copy(), wx=wx.copy(), wy=wy.copy(),
                                   tau=tau, sigma=sigma, omega=S.omega0, inner=nin,
-                                  eps_in=eps_in, k=k))
+                                  eps_in=eps_in, k=k, check=end, restart=end, E=None))
             eps_in = min(eps_in, max(st.gamma_in * float(np.linalg.norm(wx - x)) / tau,
                                      st.eps_min))
             xb = (k / (k + 1.0)) * xb + wx / (k + 1.0)

@@ -259,6 +259,11 @@ int upload_instance(Handle* h, Instance* I) {
   I->n_warm = 2L * ((long)H.wave_start.size() + (long)H.lane_start.size());
   V.warm = B.alloc<double>(I->n_warm);
   V.xb = V.yb = V.Axb = nullptr;
+  if (h->s.scheme == PDHCG_SCHEME_AVG) {
+    V.xb = B.alloc<double>(n);
+    V.yb = B.alloc<double>(m);
+    V.Axb = B.alloc<double>(m);
+  }
   I->scratch = B.alloc<double>(2048 + 2);
   I->ctl = B.alloc<Ctl>(1);
   I->bar = nullptr;   // allocated with the grid size below
@@ -708,7 +713,7 @@ struct Carve {
   }
 };
 
-void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D) {
+void carve_instance(const HostInstance& H, int trace_cap, bool avg, Carve& c, InstDesc& D) {
   const long n = H.n, m = H.m;
   DevProblem& P = D.P;
   P = DevProblem{};
@@ -773,6 +778,11 @@ void carve_instance(const HostInstance& H, int trace_cap, Carve& c, InstDesc& D)
   V.t2 = c.take<double>(n);
   D.n_warm = 2 * (P.n_wave + P.n_lane);
   V.warm = c.take<double>(D.n_warm);
+  if (avg) {
+    V.xb = c.take<double>(n);
+    V.yb = c.take<double>(m);
+    V.Axb = c.take<double>(m);
+  }
   V.partials = c.take<double>(SL_COUNT);
   D.T = TraceBufs{};
   if (trace_cap > 0) {
@@ -856,7 +866,7 @@ int setup_batch(Handle* h) {
   for (int i = 0; i < count; ++i) {
     Carve c;
     InstDesc tmp{};
-    carve_instance(h->inst[i]->H, cap, c, tmp);
+    carve_instance(h->inst[i]->H, cap, h->s.scheme == PDHCG_SCHEME_AVG, c, tmp);
     base[i + 1] = base[i] + ((c.off + 255) & ~(size_t)255);
   }
   B->arena = B->mem.alloc<char>(base[count]);
@@ -883,7 +893,7 @@ int setup_batch(Handle* h) {
       Carve c;
       c.stage = stage.data() + o;
       c.dev = (uintptr_t)(B->arena + base[i]);
-      carve_instance(h->inst[i]->H, cap, c, B->desc[i]);
+      carve_instance(h->inst[i]->H, cap, h->s.scheme == PDHCG_SCHEME_AVG, c, B->desc[i]);
     }
     int rc = flush(count);
     if (rc != PDHCG_OK) return rc;
@@ -1003,7 +1013,8 @@ int capture_batch(Handle* h) {
   hipError_t e = launch_batch_reset(B->d_desc, B->count, B->d_queue, B->cap);
   if (e == hipSuccess) e = launch_batch(batch_args(h, h->s.max_iter), B->cones, B->grid, B->cap);
   if (e == hipSuccess)
-    e = launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy, B->cap);
+    e = launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy,
+                            h->s.scheme == PDHCG_SCHEME_AVG ? 1 : 0, B->cap);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(B->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -1100,7 +1111,9 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   *out = nullptr;
   if (!probs || !s || count < 1) return PDHCG_E_ARG;
   if (s->tol <= 0 || s->check_every < 1 || s->j_max < 1 || s->max_iter < 0 ||
-      !(s->rho >= 0.5 && s->rho <= 1.0) || s->power_iters < 0 || s->scheme != PDHCG_SCHEME_RH ||
+      !(s->rho >= 0.5 && s->rho <= 1.0) || s->power_iters < 0 ||
+      (s->scheme != PDHCG_SCHEME_RH && s->scheme != PDHCG_SCHEME_AVG) ||
+      (s->scheme == PDHCG_SCHEME_AVG && (s->avg_epoch < 1 || s->precision != PDHCG_PREC_FP64)) ||
       (s->precision != PDHCG_PREC_FP64 && s->precision != PDHCG_PREC_FP32) || s->trace_iters < 0)
     return PDHCG_E_ARG;
   if (count > 1 && s->precision != PDHCG_PREC_FP64) return PDHCG_E_ARG;   // batches are FP64
@@ -1279,12 +1292,15 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
     report_phases(dpt, I->grid);
     (void)hipFree(dpt);
   }
-  // results (unscaled)
-  const double* W = I->P.q_diag ? I->V.wx : I->V.u;
+  // results (unscaled): the last PDHG candidate, or for averaged epochs the
+  // state, which is the epoch average after the last restart
+  const bool avg = h->s.scheme == PDHCG_SCHEME_AVG;
+  const double* W = avg ? I->V.x : (I->P.q_diag ? I->V.wx : I->V.u);
+  const double* Wy = avg ? I->V.y : I->V.wy;
   std::vector<double> wx(n), wy(m);
   if (c.ktot > 0) {
     HIPCHK(hipMemcpyAsync(wx.data(), W, n * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (m > 0) HIPCHK(hipMemcpyAsync(wy.data(), I->V.wy, m * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (m > 0) HIPCHK(hipMemcpyAsync(wy.data(), Wy, m * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
   finish_result(H, c, status, wx.data(), wy.data(), I->P.eta, h->setup_s, res);
@@ -1350,7 +1366,8 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
     pa.ptimes = dpt;
     HIPCHK(launch_batch_reset(B->d_desc, B->count, B->d_queue, st));
     HIPCHK(launch_batch(pa, B->cones, B->grid, st));
-    HIPCHK(launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy, st));
+    HIPCHK(launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy,
+                               h->s.scheme == PDHCG_SCHEME_AVG ? 1 : 0, st));
   } else {
     HIPCHK(hipGraphLaunch(B->exec, st));
   }

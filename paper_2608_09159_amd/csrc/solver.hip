@@ -799,13 +799,81 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
   // P needs the neighbours' s for <s, P s>: two)
   const double rho = S.rho;
   const int La = own.la, Lr = own.lr;
+  // averaged epochs (Alg. 1): fixed step sizes, plain PDHG steps
+  // z = T(z), running Cesaro averages of x, y and A x, and at the end of
+  // each epoch (or at max_iter) a restart from the average with the KKT
+  // check taken on it
+  const bool avg = std::is_same<MV, double>::value && S.scheme == PDHCG_SCHEME_AVG;   // FP64 only
+
+  // KKT dual part at (X, Y) with R^ X = hX: the dual slack
+  // s = Q^ X + c^ - A^T Y on own coordinates, <X, Q^ X> and ||Pi_K(-s)||^2
+  // (unscaled) into the partial slots SL_XQX, SL_RD2
+  auto dual_check = [&](const double* X, const double* Y, const double* hX) __attribute__((always_inline)) {
+    if (own.atperm) spmv_classes(P.AT_ptr, P.AT_col, P.AT_val, Y, V.t1, own.atperm, own.atseg);
+    else spmv_range(P.AT_ptr, P.AT_col, P.AT_val, Y, V.t1, c0, c1, La);
+    if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, X, V.t2, c0, c1, La);
+    if (!P.q_diag) make_ht(L, P, hX);
+    else __syncthreads();
+    double acc[2] = {0.0, 0.0};
+    for_range(c0, c1, [&](long i, bool act) {
+      if (!act) return;
+      const double wi = X[i];
+      double qw;
+      if (P.q_diag) {
+        qw = P.qd[i] * wi;
+      } else {
+        qw = P.p_diag ? P.Pd[i] * wi : (P.P_ptr ? V.t2[i] : 0.0);
+        qw += r_dot(R64, r, i, L.ht);
+      }
+      const double si = qw + P.c[i] - V.t1[i];
+      acc[0] += wi * qw;                               // SL_XQX
+      const double so = P.nu_c * P.Sx[i] * si;
+      const uint8_t ct = P.ctype[i];
+      if (ct == CT_FREE) acc[1] += so * so;
+      else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
+      else V.s[i] = si;
+    });
+    if (has_items) {
+      __syncthreads();
+      project_items(P, IT, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb,
+                    V.warm + (P.n_wave + P.n_lane));
+      for_item_coords(P, IT, [&](long i, bool act) {
+        if (act) {
+          const double f = P.nu_c * P.Sx[i] * V.zb[i];
+          acc[1] += f * f;
+        }
+      });
+    }
+    const int sl[2] = {SL_XQX, SL_RD2};
+    block_store(L, acc, sl, 2, part, G, rank);
+  };
+
+  // residuals, objectives and status from the reduced slots SL_RP2, SL_RD2,
+  // SL_XQX, SL_CX, SL_BY (thread 0)
+  auto kkt_status = [&](Ctl& C, bool bad) __attribute__((always_inline)) {
+    const double* sc = L.scal;
+    const double scale = P.nu_b * P.nu_c;
+    C.rel_p = sqrt(sc[SL_RP2]) / (1.0 + P.norm_b);
+    C.rel_d = sqrt(sc[SL_RD2]) / (1.0 + P.norm_c);
+    C.pobj = scale * (0.5 * sc[SL_XQX] + sc[SL_CX]);
+    C.dobj = scale * (sc[SL_BY] - 0.5 * sc[SL_XQX]);
+    C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
+    if (bad || !isfinite(C.rel_p) || !isfinite(C.rel_d) || !isfinite(C.rel_gap)) {
+      C.status = PDHCG_NUMERICAL;
+    } else if (fmax(C.rel_p, fmax(C.rel_d, C.rel_gap)) <= S.tol) {
+      C.status = PDHCG_OPTIMAL;
+    } else if (A.deadline != 0ull && wall_clock64() > A.deadline) {
+      C.status = PDHCG_TIME_LIMIT;
+    }
+  };
 
   while (L.C.ktot < A.stop_at && L.C.status == 0) {
     const double omega = L.C.omega;
     const double tau = P.eta / omega, sigma = P.eta * omega;
     const long long k = L.C.k;
     const long long kt1 = L.C.ktot + 1;
-    const bool check = (k == 0) || (kt1 % S.check_every == 0) || (kt1 >= S.max_iter);
+    const bool ep_end = avg && ((k + 1 >= (long long)S.avg_epoch) || (kt1 >= S.max_iter));
+    const bool check = avg ? ep_end : ((k == 0) || (kt1 % S.check_every == 0) || (kt1 >= S.max_iter));
     const double eps_in = L.C.eps_in;
     const bool tracing = TB.cap > 0 && L.C.ktot < TB.cap;
     double* W = P.q_diag ? V.wx : V.u;   // the primal candidate w_x
@@ -1041,6 +1109,84 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     tmark(L, prof, PT_P6);
     const double c1h = (double)(k + 1) / (double)(k + 2);
     const double c3h = 1.0 / (double)(k + 2);
+    if (avg) {
+      // w_y, then z = T(z): x = w_x, y = w_y, A x = A w_x, and the running
+      // averages zbar = k/(k+1) zbar + w/(k+1) (eq. theory-epoch-average);
+      // at the epoch's end the state restarts from zbar, and the primal
+      // residual, <b, ybar> and <c, xbar> of the check are accumulated
+      const double kd = (double)k;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
+        const double aw = spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
+        if (act && sub == 0) {
+          const double yl = V.y[l], axl = V.Ax[l];
+          const double wy = yl + sigma * (P.b[l] - (2.0 * aw - axl));
+          V.wy[l] = wy;
+          V.Aw[l] = aw;
+          if (tracing) TB.wy[L.C.ktot * m + l] = wy;
+          const double yb = k == 0 ? wy : (kd / (kd + 1.0)) * V.yb[l] + wy / (kd + 1.0);
+          const double axb = k == 0 ? aw : (kd / (kd + 1.0)) * V.Axb[l] + aw / (kd + 1.0);
+          V.yb[l] = yb;
+          V.Axb[l] = axb;
+          if (ep_end) {
+            V.y[l] = yb;
+            V.Ax[l] = axb;
+            const double rp = P.nu_b * (axb - P.b[l]) / P.Sy[l];
+            acc[1] += rp * rp;                           // SL_RP2
+            acc[2] += P.b[l] * yb;                       // SL_BY
+          } else {
+            V.y[l] = wy;
+            V.Ax[l] = aw;
+          }
+        }
+      });
+      for_range(c0, c1, [&](long i, bool act) {
+        if (!act) return;
+        const double xi = V.x[i], wi = W[i];
+        if (tracing) TB.wx[L.C.ktot * n + i] = wi;
+        acc[0] += (wi - xi) * (wi - xi);                 // SL_XMOV2
+        const double xb = k == 0 ? wi : (kd / (kd + 1.0)) * V.xb[i] + wi / (kd + 1.0);
+        V.xb[i] = xb;
+        if (ep_end) {
+          V.x[i] = xb;
+          acc[3] += P.c[i] * xb;                         // SL_CX
+        } else {
+          V.x[i] = wi;
+        }
+      });
+      const int sl[4] = {SL_XMOV2, SL_RP2, SL_BY, SL_CX};
+      block_store(L, acc, sl, ep_end ? 4 : 1, part, G, rank);
+      SYNC_OR_EXIT();
+      if (tid == 0) {
+        L.C.inner_total += jcount;
+        L.C.ktot = kt1;
+      }
+      team_reduce(L, part, G, sl, ep_end ? 4 : 1);
+      if (tid == 0) {
+        L.C.eps_in = fmin(L.C.eps_in, fmax(S.gamma_in * sqrt(L.scal[SL_XMOV2]) / tau, S.eps_min));
+      }
+      // R^ x of the new state: R^ w_x is the last inner R^ u; its running
+      // average is kept beside the others
+      if ((int)tid < r) {
+        const double hb = k == 0 ? L.hu[tid] : (kd / (kd + 1.0)) * L.C.hxb[tid] + L.hu[tid] / (kd + 1.0);
+        L.C.hxb[tid] = hb;
+        L.C.hx[tid] = ep_end ? hb : L.hu[tid];
+      }
+      __syncthreads();
+      if (!ep_end) {
+        if (tid == 0) {
+          L.C.k = k + 1;
+          if (tracing && rank == 0) {
+            double* t = TB.sc + (kt1 - 1) * 8;
+            t[0] = tau; t[1] = sigma; t[2] = omega; t[3] = eps_in;
+            t[4] = jcount; t[5] = 0.0; t[6] = 0.0; t[7] = 0.0;
+          }
+        }
+        __syncthreads();
+        continue;
+      }
+      // end of the epoch: the KKT check below runs on the new state zbar
+    } else {
     {
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
@@ -1127,58 +1273,36 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       __syncthreads();
       continue;
     }
+    }
 
     // ---------------------------------------------------------- check
+    // reflected Halpern: on the candidate w (R^ w_x is the last inner R^ u;
+    // diagonal Q has r = 0); averaged epochs: on the new state zbar
     tmark(L, prof, PT_CHECK);
-    {
+    if (!avg) {
       const int sl[8] = {SL_DY2, SL_ADXDY, SL_RP2, SL_BY, SL_MOVY2, SL_DX2, SL_MOVX2, SL_CX};
       team_reduce(L, part, G, sl, 8);
     }
-    {
-      // dual slack s = Q w + c - A^T w_y on own coordinates; R^ w_x is the
-      // last inner R^ u (diagonal Q has r = 0)
-      if (own.atperm) spmv_classes(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, own.atperm, own.atseg);
-      else spmv_range(P.AT_ptr, P.AT_col, P.AT_val, V.wy, V.t1, c0, c1, La);
-      if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, W, V.t2, c0, c1, La);
-      if (!P.q_diag) make_ht(L, P, L.hu);
-      else __syncthreads();
-      double acc[2] = {0.0, 0.0};
-      for_range(c0, c1, [&](long i, bool act) {
-        if (!act) return;
-        const double wi = W[i];
-        double qw;
-        if (P.q_diag) {
-          qw = P.qd[i] * wi;
-        } else {
-          qw = P.p_diag ? P.Pd[i] * wi : (P.P_ptr ? V.t2[i] : 0.0);
-          qw += r_dot(R64, r, i, L.ht);
-        }
-        const double si = qw + P.c[i] - V.t1[i];
-        acc[0] += wi * qw;                               // SL_XQX
-        const double so = P.nu_c * P.Sx[i] * si;
-        const uint8_t ct = P.ctype[i];
-        if (ct == CT_FREE) acc[1] += so * so;
-        else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
-        else V.s[i] = si;
-      });
-      if (has_items) {
-        __syncthreads();
-        project_items(P, IT, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb,
-                      V.warm + (P.n_wave + P.n_lane));
-        for_item_coords(P, IT, [&](long i, bool act) {
-          if (act) {
-            const double f = P.nu_c * P.Sx[i] * V.zb[i];
-            acc[1] += f * f;
-          }
-        });
-      }
-      const int sl[2] = {SL_XQX, SL_RD2};
-      block_store(L, acc, sl, 2, part, G, rank);
-    }
+    dual_check(avg ? V.x : W, avg ? V.y : V.wy, avg ? L.C.hx : L.hu);
     SYNC_OR_EXIT();
     {
       const int sl[2] = {SL_XQX, SL_RD2};
       team_reduce(L, part, G, sl, 2);
+    }
+    if (avg) {
+      if (tid == 0) {
+        kkt_status(L.C, false);
+        L.C.k = 0;
+        L.C.restarts += 1;
+        if (tracing && rank == 0) {
+          double* t = TB.sc + (kt1 - 1) * 8;
+          t[0] = tau; t[1] = sigma; t[2] = omega; t[3] = eps_in;
+          t[4] = jcount; t[5] = 1.0; t[6] = 1.0; t[7] = 0.0;
+        }
+      }
+      __syncthreads();
+      if (L.C.status != 0) break;
+      continue;
     }
     if (tid == 0) {
       Ctl& C = L.C;
@@ -1191,19 +1315,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
                 ((double)(k + 1) >= S.beta_a * (double)kt1);
       C.Eprev = E;
       C.lastE = E;
-      const double scale = P.nu_b * P.nu_c;
-      C.rel_p = sqrt(sc[SL_RP2]) / (1.0 + P.norm_b);
-      C.rel_d = sqrt(sc[SL_RD2]) / (1.0 + P.norm_c);
-      C.pobj = scale * (0.5 * sc[SL_XQX] + sc[SL_CX]);
-      C.dobj = scale * (sc[SL_BY] - 0.5 * sc[SL_XQX]);
-      C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
-      if (!isfinite(E) || !isfinite(C.rel_p) || !isfinite(C.rel_d) || !isfinite(C.rel_gap)) {
-        C.status = PDHCG_NUMERICAL;
-      } else if (fmax(C.rel_p, fmax(C.rel_d, C.rel_gap)) <= S.tol) {
-        C.status = PDHCG_OPTIMAL;
-      } else if (A.deadline != 0ull && wall_clock64() > A.deadline) {
-        C.status = PDHCG_TIME_LIMIT;
-      }
+      kkt_status(C, !isfinite(E));
       if (C.status == 0 && rs) {
         const double dxm = sqrt(sc[SL_MOVX2]), dym = sqrt(sc[SL_MOVY2]);
         if (dxm > 1e-12 && dym > 1e-12) {
@@ -1529,15 +1641,19 @@ __global__ __launch_bounds__(BLOCK) void batch_power_kernel(const InstDesc* desc
 }
 
 // pack every instance's candidate (w_x, w_y) into contiguous outputs
+// the result of each instance: the last PDHG candidate (reflected Halpern)
+// or the state, which is the epoch average after the last restart (averaged
+// epochs)
 __global__ __launch_bounds__(BLOCK) void batch_gather_kernel(const InstDesc* desc, int count,
                                                             const long* offx, const long* offy,
-                                                            double* ox, double* oy) {
+                                                            double* ox, double* oy, int avg) {
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const InstDesc& D = desc[i];
-    const double* W = D.P.q_diag ? D.V.wx : D.V.u;
+    const double* X = avg ? D.V.x : (D.P.q_diag ? D.V.wx : D.V.u);
+    const double* Y = avg ? D.V.y : D.V.wy;
     const long n = D.P.n, m = D.P.m;
-    for (long j = threadIdx.x; j < n; j += BLOCK) ox[offx[i] + j] = W[j];
-    for (long l = threadIdx.x; l < m; l += BLOCK) oy[offy[i] + l] = D.V.wy[l];
+    for (long j = threadIdx.x; j < n; j += BLOCK) ox[offx[i] + j] = X[j];
+    for (long l = threadIdx.x; l < m; l += BLOCK) oy[offy[i] + l] = Y[l];
   }
 }
 
@@ -1739,10 +1855,10 @@ hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double
 }
 
 hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx, const long* offy,
-                               double* ox, double* oy, hipStream_t st) {
+                               double* ox, double* oy, int avg, hipStream_t st) {
   const int grid = std::max(1, std::min(count, 4096));
   hipLaunchKernelGGL(batch_gather_kernel, dim3(grid), dim3(BLOCK), 0, st, desc, count, offx, offy, ox,
-                     oy);
+                     oy, avg);
   return hipGetLastError();
 }
 

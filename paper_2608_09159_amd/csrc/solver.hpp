@@ -32,6 +32,6 @@ hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t
 hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipStream_t st);
 hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double* out, hipStream_t st);
 hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx, const long* offy,
-                               double* ox, double* oy, hipStream_t st);
+                               double* ox, double* oy, int avg, hipStream_t st);
 
 }  // namespace pdhcg

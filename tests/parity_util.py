@@ -58,7 +58,7 @@ def assert_trace_matches(name, tr, o):
         assert tr["inner"][k] == ot["inner"], (prob_name, k, "inner")
         assert bool(tr["check"][k]) == bool(ot["check"]), (prob_name, k, "check")
         assert bool(tr["restart"][k]) == bool(ot["restart"]), (prob_name, k, "restart")
-        if ot["check"]:
+        if ot["check"] and ot["E"] is not None:
             assert tr["E"][k] == pytest.approx(ot["E"], rel=1e-9, abs=1e-300)
 
 
