@@ -276,6 +276,22 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count);
 int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha,
                         const double* r, const double* metric, double* out);
 
+/* pdhcg_project_cones for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same projections with DEVICE pointers, issued
+ * asynchronously on `stream` (hipStream_t as void*, NULL = null stream), no
+ * allocation, no memset and no host synchronisation.  r, out: count*dim
+ * doubles; metric: count*dim or NULL; alpha: count (POW) -- all device
+ * memory owned by the caller.  The per-block flags (metric constant on the
+ * block) go to a static device array of the library, one per device, held
+ * until the process ends: count may not exceed 4,194,304 blocks
+ * (PDHCG_E_ARG otherwise).  Every call on a device writes that device's
+ * array, so calls that overlap on one device (different streams, threads)
+ * race; serialise them.  Metric and alpha values are not checked (invalid
+ * ones give NaN).  Errors: PDHCG_E_ARG, PDHCG_E_CONE, PDHCG_E_HIP.         */
+int pdhcg_project_cones_noalloc(int32_t type, int32_t dim, int64_t count, const double* alpha,
+                                const double* r, const double* metric, double* out, void* stream);
+
 /* Release every host and device resource of h (NULL is a no-op).          */
 void pdhcg_free(void* h);
 

@@ -16,6 +16,8 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
     Handle.scaling() -> dict                  (pdhcg_get_scaling)
     Handle.free()                             (pdhcg_free)
     project_cones(kind, r, metric, alpha)     (pdhcg_project_cones, diagnostic)
+    project_cones_noalloc(kind, r, out, ...)  (pdhcg_project_cones_noalloc: device
+                                               tensors, no allocation)
     MLP(dims, max_batch).forward / .train_step / .set_params / .get_params /
         .grads / .free                        (pdhcg_mlp_*: the warm-start
                                                network's BF16 matrix-core kernels)
@@ -96,7 +98,8 @@ _LIB = None
 
 EXPORTS = ("pdhcg_default_settings", "pdhcg_setup", "pdhcg_solve", "pdhcg_solve_batch",
            "pdhcg_get_trace", "pdhcg_get_scaling", "pdhcg_free", "pdhcg_strerror",
-           "pdhcg_version", "pdhcg_last_cone_failure", "pdhcg_project_cones", "pdhcg_mlp_create", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
+           "pdhcg_version", "pdhcg_last_cone_failure", "pdhcg_project_cones",
+           "pdhcg_project_cones_noalloc", "pdhcg_mlp_create", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
            "pdhcg_mlp_forward", "pdhcg_mlp_train_step", "pdhcg_mlp_get_grads", "pdhcg_mlp_free")
 
 
@@ -141,6 +144,8 @@ def load(path=None):
     lib.pdhcg_version.restype = C.c_char_p
     lib.pdhcg_last_cone_failure.argtypes = [_dp, C.POINTER(C.c_int64)]
     lib.pdhcg_project_cones.argtypes = [C.c_int32, C.c_int32, C.c_int64, _dp, _dp, _dp, _dp]
+    lib.pdhcg_project_cones_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     _fp = C.POINTER(C.c_float)
     lib.pdhcg_mlp_create.argtypes = [C.c_int32, _i32p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.pdhcg_mlp_set_params.argtypes = [C.c_void_p, C.c_int32, _fp, _fp]
@@ -334,6 +339,29 @@ def project_cones(kind, r, metric=None, alpha=None):
     _check(load().pdhcg_project_cones(code, dim, count, _ptr(a, C.c_double), _ptr(r, C.c_double),
                                       _ptr(m, C.c_double), _ptr(out, C.c_double)),
            "pdhcg_project_cones")
+    return out
+
+
+def project_cones_noalloc(kind, r, out, metric=None, alpha=None, stream=None):
+    """pdhcg_project_cones_noalloc on torch CUDA float64 tensors: r and out
+    (count, dim), metric the same shape or None, alpha (count,) for POW;
+    issued on `stream` (a torch stream, or None for the null stream) without
+    any allocation.  Returns out."""
+    code = CONE_CODES[kind] if isinstance(kind, str) else int(kind)
+
+    def dev(t, shape):
+        if t is None:
+            return None
+        if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
+                and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous CUDA float64 tensor of shape {shape}")
+        return t.data_ptr()
+
+    count, dim = int(r.shape[0]), int(r.shape[1])
+    st = getattr(stream, "cuda_stream", stream)
+    _check(load().pdhcg_project_cones_noalloc(code, dim, count, dev(alpha, (count,)), dev(r, (count, dim)),
+                                              dev(metric, (count, dim)), dev(out, (count, dim)), st),
+           "pdhcg_project_cones_noalloc")
     return out
 
 

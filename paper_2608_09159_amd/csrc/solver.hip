@@ -39,6 +39,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1809,6 +1810,20 @@ hipError_t read_cone_failure(double rec[8], unsigned* count) {
   return hipMemcpyFromSymbol(rec, HIP_SYMBOL(g_cone_fail), 8 * sizeof(double));
 }
 
+// flags[b] = 1 when the metric is absent or constant on block b (the
+// Euclidean formula applies, Pi^{cI} = Pi^I), else 0
+__global__ __launch_bounds__(BLOCK) void euclid_flags_kernel(long count, int dim, const double* m,
+                                                             unsigned char* flags) {
+  for (long b = (long)blockIdx.x * BLOCK + threadIdx.x; b < count; b += (long)gridDim.x * BLOCK) {
+    bool c = true;
+    if (m) {
+      const double* mb = m + b * (long)dim;
+      for (int j = 1; j < dim; ++j) c = c && (mb[j] == mb[0]);
+    }
+    flags[b] = c ? 1 : 0;
+  }
+}
+
 hipError_t launch_project(int type, int dim, long count, const double* alpha, const double* r,
                           const double* m, const unsigned char* euclid, double* out, hipStream_t st) {
   if (count <= 0) return hipSuccess;
@@ -1862,4 +1877,61 @@ hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// the allocation-free projection entry point: its per-block flags live in a
+// static device array (one copy per device, held until the process ends)
+// whose device address is looked up once per device
+// ---------------------------------------------------------------------------
+constexpr long kNoAllocMaxBlocks = 1L << 22;   // 4 MiB of flags per device
+static __device__ __align__(256) unsigned char scratch[kNoAllocMaxBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// device address of `scratch` on the current device (looked up on the first
+// call per device; the host-side name is not a device address)
+static hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+long noalloc_max_blocks() { return kNoAllocMaxBlocks; }
+
 }  // namespace pdhcg
+
+extern "C" int pdhcg_project_cones_noalloc(int32_t type, int32_t dim, int64_t count, const double* alpha,
+                                           const double* r, const double* metric, double* out,
+                                           void* stream) {
+  using namespace pdhcg;
+  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;
+  if ((type == PDHCG_CONE_RSOC && dim < 2) ||
+      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) && dim != 3))
+    return PDHCG_E_CONE;
+  if (count > kNoAllocMaxBlocks) return PDHCG_E_ARG;
+  if (count == 0) return PDHCG_OK;
+  if (!r || !out || (type == PDHCG_CONE_POW && !alpha)) return PDHCG_E_ARG;
+  void* flags = nullptr;
+  if (scratch_address(&flags) != hipSuccess) return PDHCG_E_HIP;
+  hipStream_t st = (hipStream_t)stream;
+  const long grid = std::max<long>(1, std::min<long>((count + BLOCK - 1) / BLOCK, 4096));
+  hipLaunchKernelGGL(euclid_flags_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, st, (long)count, (int)dim, metric,
+                     (unsigned char*)flags);
+  if (hipGetLastError() != hipSuccess) return PDHCG_E_HIP;
+  if (launch_project(type, dim, (long)count, alpha, r, metric, (const unsigned char*)flags, out, st) != hipSuccess)
+    return PDHCG_E_HIP;
+  return PDHCG_OK;
+}
