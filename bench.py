@@ -1,12 +1,27 @@
-"""Benchmark: time-to-1e-6 relative KKT and PDHG iterations/s of the MI355X
-solver on the mixed-cone SOCP/QCQP workload (n = 1e5, m = 5e4, ~1e6 nnz,
-2000 SOC(20) + 1000 RSOC(10) + 500 EXP + 500 POW + R+, Q = diag + rank-10).
+"""Benchmark of the MI355X restarted-PDHG solver.
 
-One step = one full solve from a cold start to the tolerance (every row of
-the hot path: prox with Jacobi projected-BB inner loop, batched cone
-projections, A and A^T products, reflected-Halpern update, restarts, device
-KKT checks).  Setup (rescaling, A^T, power iteration) is outside the timed
-region; problem data is resident in HBM when timing starts.
+Default line: the large sparse QP (n = 1e7 R+ columns, m = 5e6 rows, 5.1e7
+nonzeros with power-law column degrees, 10% slack columns; Q sparse with 3e7
+nonzeros), the one workload whose working set (~3.5 GB) is far larger than
+the caches, so the HBM roofline is the bound.  One step = one solve from a
+cold start over a fixed budget of outer iterations (--budget, default 256;
+every row of the hot path runs: A^T product, Jacobi projected-BB inner loop
+with the P product, A product and dual update, reflected-Halpern update,
+restarts, device KKT checks).  The method does not reach 1e-4 on this
+instance within minutes, so the line reports iterations/s over the budget and
+the relative KKT reached; time to tolerance is reported for the mixed-cone
+workload among the variants.  Setup (rescaling, A^T, power iteration) is
+outside the timed region; problem data is resident in HBM when timing starts.
+
+Variants (default line): FP32 bulk on the same instance and budget, the
+mixed-cone SOCP/QCQP solve to 1e-6 in FP64 and FP32 bulk, and the batch of
+4096 portfolio QPs against a per-instance loop.  --workload selects another
+workload as the main line (mixed_cone, fisher, tiny_qp, portfolio_batch,
+fisher_warm, mlp_train).
+
+cpu_baseline: the oracle as it stands, one thread, on the first outer
+iterations of the same instance, run in a child process started before the
+GPU work (its setup, which is not timed, overlaps the GPU runs).
 
 Prints one JSON line.  `--gpus N` with N > 1 is rejected: this build targets a
 single GPU.
@@ -29,15 +44,12 @@ HBM_PEAK_GBS = 8000.0
 BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 # HBM traffic of one solve_kernel launch on the default workload, from two
-# rocprofv3 counter runs (FETCH_SIZE x 1.99967, WRITE_SIZE x 1.0: the factors
-# that make a 256 MiB device copy read and write 256 MiB).  Valid only for the
-# kernel sources whose hash is recorded, at the recorded grid; otherwise the
-# bench reports null.
-MEASURED_TRAFFIC = {
-    "workload": "mixed_cone", "grid": 256, "iterations": 448,
-    "sources_sha256": "4950cf1b8289aae72b87fceaee366390725576d3e7155baea26b108f6ac0281d",
-    "bytes_per_launch": 10552558.0 * 1024 * 1.99967 + 11241005.4375 * 1024 * 1.0,
-}
+# rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE scaled by the factors
+# that make a 256 MiB device copy read and write 256 MiB), as a dict with the
+# workload, grid, iterations per launch, the kernel sources' sha256 and
+# bytes_per_launch.  Valid only for the recorded kernel sources, grid and
+# iteration count; otherwise (and while None) the bench reports null.
+MEASURED_TRAFFIC = None
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
 
@@ -64,6 +76,32 @@ def workload(name):
     if name == "portfolio_batch":
         return synth.portfolio_batch(4096), "4096 portfolio QPs n~U[50,2000] k~U[5,20]"
     raise ValueError(name)
+
+
+def method_bytes_model(prob, iters, inner_total, checks):
+    """Algorithmic HBM bytes of the method over `iters` outer iterations
+    with `inner_total` projected-BB steps and `checks` KKT checks: every
+    product reads its matrix once (FP64 value + int32 column, 12 bytes per
+    nonzero, and 4 bytes per row pointer), its input vector once (an ideal
+    gather) and writes its output once; A z is kept by recurrence.
+        A^T product + prox input     12 nnz(A) + 4n + 8m + 16n
+        A product + dual candidate   12 nnz(A) + 4m + 8n + 40m
+        reflected-Halpern update     32n + 64m
+        diagonal prox                32n
+        each JBB inner step          12 nnz(P) + 16 r n + 92n
+    so 24 nnz(A) + 60n + 116m per outer iteration plus the prox; a check
+    adds one A^T product and one Q product (12 nnz(P) + 16 r n + 16n)."""
+    n, m = prob.n, prob.m
+    nnzA = prob.A.nnz
+    nnzP = 0 if prob.P is None else prob.P.nnz
+    r = 0 if prob.R is None else prob.R.shape[0]
+    diag_q = r == 0 and (prob.P is None or np.all(prob.P.tocoo().row == prob.P.tocoo().col))
+    b_at = 12 * nnzA + 4 * n + 8 * m + 16 * n
+    b_a = 12 * nnzA + 4 * m + 8 * n + 40 * m
+    b_halpern = 32 * n + 64 * m
+    b_q = 12 * nnzP + 16 * r * n + 16 * n
+    prox = iters * 32 * n if diag_q else inner_total * (12 * nnzP + 16 * r * n + 92 * n)
+    return iters * (b_at + b_a + b_halpern) + prox + checks * (b_at + b_q)
 
 
 def bytes_model(prob, iters, inner_total, checks):
@@ -128,6 +166,18 @@ def same_footprint_context(prob, s_per_iter, reps=20):
             "same_footprint_copy_GBs": 2.0 * 8.0 * half / t / 1e9}
 
 
+def log(msg):
+    """Progress of the phases, on stderr (the JSON line goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The oracle as it stands, single thread, on the first outer iterations
     of the same instance; iterations/s."""
@@ -137,19 +187,39 @@ def cpu_baseline(prob, budget_s=15.0):
         t0 = time.perf_counter()
         S = pdhg.setup(prob, pdhg.Settings())
         t_setup = time.perf_counter() - t0
+        log(f"oracle setup done ({t_setup:.1f} s)")
         iters = 2
         while True:
             t0 = time.perf_counter()
             r = pdhg.solve(prob, pdhg.Settings(max_iter=iters), S=S)
             dt = time.perf_counter() - t0
-            if dt >= 0.6 * budget_s or iters >= 100000:
+            log(f"oracle: {r.iterations} outer iterations in {dt:.1f} s")
+            if dt >= 0.6 * budget_s or iters >= 100000 or r.status != "MAX_ITER":
                 break
             grow = min(max(1.25, budget_s / max(dt, 1e-3)), 8.0)
             iters = int(min(iters * grow, 100000))
     return dict(value=r.iterations / dt, unit="PDHG iters/s", cores=1, kind="oracle",
+                host_cores=host_cores(),
                 sample=f"first {r.iterations} outer iterations of the same instance "
                        f"({dt:.1f}s, {r.inner_iterations} inner steps; setup {t_setup:.1f}s "
                        f"excluded); NumPy/SciPy FP64, BLAS pinned to 1 thread")
+
+
+def start_cpu_child(args):
+    """The cpu_baseline leg in a child process (no GPU use), so the oracle's
+    setup overlaps the GPU runs; returns the Popen handle."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--workload", args.workload,
+           "--cpu-budget", str(args.cpu_budget)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, env=env, text=True)
+
+
+def finish_cpu_child(proc):
+    out, _ = proc.communicate()
+    if proc.returncode != 0:
+        return {"error": f"oracle child exited with {proc.returncode}"}
+    return json.loads(out.strip().splitlines()[-1])
 
 
 def bench_batch(args, probs, wname):
@@ -347,19 +417,73 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
+def timed_solves(prob, args, budget, precision="fp64"):
+    """Setup, warm-up and the timed solves of one instance on torch's current
+    stream; returns (runs, wall seconds of the timed solves, setup seconds)."""
+    import torch
+    import paper_2608_09159_amd as pkg
+    stream = torch.cuda.current_stream()
+    extra = {"max_iter": budget} if budget > 0 else {}
+    t0 = time.perf_counter()
+    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream, precision=precision, **extra)
+    setup_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        h.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [h.solve() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h.free()
+    return runs, wall, setup_s
+
+
+def rel_kkt(r):
+    return max(r["rel_primal"], r["rel_dual"], r["rel_gap"])
+
+
+def fp32_budget_variant(prob, args, budget, wall64, last64):
+    """FP32 bulk on the same instance and iteration budget: time per
+    iteration against FP64, the relative KKT reached, and the distance of
+    its iterate from the FP64 one at the same iteration count."""
+    runs, wall, _ = timed_solves(prob, args, budget, precision="fp32")
+    r = runs[-1]
+    return {"iterations": r["iterations"], "time_per_iteration_ms": 1e3 * wall / sum(x["iterations"] for x in runs),
+            "speedup_per_iteration_vs_fp64": wall64 / wall,
+            "rel_kkt": rel_kkt(r), "rel_kkt_fp64": rel_kkt(last64), "status": r["status"],
+            "x_rel_err_vs_fp64": float(np.linalg.norm(r["x"] - last64["x"]) / max(np.linalg.norm(last64["x"]), 1e-300)),
+            "kernel_ms_per_iteration": 1e3 * sum(x["kernel_s"] for x in runs) / sum(x["iterations"] for x in runs)}
+
+
+def mixed_cone_variant(args):
+    """The mixed-cone SOCP/QCQP instance solved to the tolerance in FP64 and
+    in FP32 bulk with the FP64 polish."""
+    prob, wname = workload("mixed_cone")
+    runs, wall, _ = timed_solves(prob, args, 0)
+    t64 = wall / args.steps
+    out = {"workload": wname, "time_to_tol_s": t64, "iterations": runs[-1]["iterations"],
+           "inner_iterations": runs[-1]["inner_iterations"], "status": runs[-1]["status"],
+           "rel_kkt": rel_kkt(runs[-1]), "iters_per_s": sum(r["iterations"] for r in runs) / wall,
+           "kernel_ms_per_solve": 1e3 * sum(r["kernel_s"] for r in runs) / args.steps}
+    out["fp32_bulk"] = fp32_variant(prob, args, t64, runs[-1])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mixed_cone")
+    ap.add_argument("--workload", default="large_sparse_qp")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--max-iter", type=int, default=0,
-                    help="cap on outer iterations per solve (0: none; for fixed-length profiling runs)")
+    ap.add_argument("--budget", type=int, default=-1,
+                    help="outer iterations per step (0: run to the tolerance; default: 256 for the "
+                         "large sparse QP, 0 otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP32-bulk and batched comparisons of the default line")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+                    help="skip the FP32-bulk, mixed-cone and batched comparisons of the default line")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--loop-sample", type=int, default=4096,
                     help="portfolio_batch: instances timed in the per-instance loop baseline")
     ap.add_argument("--train-instances", type=int, default=1024,
@@ -371,10 +495,19 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_child:
+        prob, _ = workload(args.workload)
+        log("oracle child: instance generated")
+        print(json.dumps(cpu_baseline(prob, args.cpu_budget)), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
               "(the 2-D partition across GPUs is design-only).", file=sys.stderr)
         sys.exit(2)
+    budget = args.budget if args.budget >= 0 else (256 if args.workload == "large_sparse_qp" else 0)
+    child = None
+    if not args.no_cpu and args.workload in ("large_sparse_qp", "mixed_cone", "fisher", "tiny_qp"):
+        child = start_cpu_child(args)
 
     import torch
     import paper_2608_09159_amd as pkg
@@ -398,34 +531,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    stream = torch.cuda.current_stream()
-    extra = {"max_iter": args.max_iter} if args.max_iter > 0 else {}
-    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream, **extra)
-    res = None
-    for _ in range(args.warmup):
-        res = h.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = []
-    for _ in range(args.steps):
-        runs.append(h.solve())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    h.free()
+    log(f"{wname}: instance generated")
+    runs, wall, setup_s = timed_solves(prob, args, budget)
+    log(f"{wname}: {args.steps} timed solves in {wall:.2f} s (setup {setup_s:.1f} s)")
     iters = sum(r["iterations"] for r in runs)
     inner = sum(r["inner_iterations"] for r in runs)
     ksum = sum(r["kernel_s"] for r in runs)
-    traffic = None
+    launches = sum(r["kernel_launches"] for r in runs)
     grid = runs[-1]["grid_dim"]
+    traffic = None
     mt = MEASURED_TRAFFIC
-    if (args.workload == mt["workload"] and kernel_sources_hash() == mt["sources_sha256"]
+    if (mt is not None and args.workload == mt["workload"] and kernel_sources_hash() == mt["sources_sha256"]
             and grid == mt["grid"] and all(r["iterations"] == mt["iterations"] for r in runs)):
         traffic = mt["bytes_per_launch"]
-    launches = sum(r["kernel_launches"] for r in runs)
     checks = sum(math.ceil(r["iterations"] / 64) + r["restarts"] + 1 for r in runs)
-    alg_bytes = bytes_model(prob, iters, inner, checks)
+    alg_bytes = method_bytes_model(prob, iters, inner, checks)
     achieved = alg_bytes / ksum / 1e9
     last = runs[-1]
+    reached = last["status"] == "OPTIMAL"
     out = {
         "metric": METRIC,
         "value": iters / wall,
@@ -440,23 +563,33 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "n": prob.n, "m": prob.m, "nnz_A": int(prob.A.nnz),
-                   "tol": args.tol, "precision": "fp64"},
-        "time_to_tol_s": wall / args.steps,
+                   "nnz_P": int(prob.P.nnz) if prob.P is not None else 0,
+                   "tol": args.tol, "precision": "fp64",
+                   "outer_iterations_per_step": budget if budget > 0 else "to tolerance"},
+        "time_to_tol_s": wall / args.steps if reached else None,
         "iterations_per_solve": iters / args.steps,
         "inner_per_solve": inner / args.steps,
         "status": last["status"],
-        "rel_kkt": max(last["rel_primal"], last["rel_dual"], last["rel_gap"]),
+        "rel_kkt": rel_kkt(last),
+        "rel_primal": last["rel_primal"], "rel_dual": last["rel_dual"], "rel_gap": last["rel_gap"],
+        "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
                      "kernel": "solve_kernel", "kernel_avg_launch_ms": 1e3 * ksum / launches,
                      "launch": [grid, runs[-1]["block_dim"]],
-                     "algorithmic_bytes_per_iteration": alg_bytes / iters},
+                     "algorithmic_bytes_per_iteration": alg_bytes / iters,
+                     "bytes_model": "method (A, A^T, P read once per product, ideal gathers)"},
     }
-    out["context"] = same_footprint_context(prob, ksum / iters)
-    if not args.no_variants and args.workload == "mixed_cone":
-        wall1 = wall / args.steps
-        out["variants"] = {"fp32_bulk": fp32_variant(prob, args, wall1, last)}
+    ctx = same_footprint_context(prob, ksum / iters)
+    ctx["kernel_pass_bytes_per_iteration"] = bytes_model(prob, iters, inner, checks) / iters
+    out["context"] = ctx
+    if not args.no_variants and args.workload == "large_sparse_qp":
+        out["variants"] = {"fp32_bulk": fp32_budget_variant(prob, args, budget, wall, last)}
+        log("fp32 bulk variant done")
+        del prob
+        out["variants"]["mixed_cone"] = mixed_cone_variant(args)
+        log("mixed-cone variant done")
         bargs = argparse.Namespace(**{**vars(args), "loop_sample": 128})
         bw, bname = workload("portfolio_batch")
         bo = bench_batch(bargs, bw, bname)
@@ -466,8 +599,12 @@ def main():
             "loop_instances_timed": bo["loop_baseline"]["instances_timed"],
             "speedup_vs_loop": bo["speedup_vs_loop"], "statuses": bo["statuses"],
             "iters_per_s": bo["value"], "roofline_frac": bo["roofline"]["frac"]}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+        log("batched variant done")
+    elif not args.no_variants and args.workload == "mixed_cone":
+        out["variants"] = {"fp32_bulk": fp32_variant(prob, args, wall / args.steps, last)}
+    if child is not None:
+        log("waiting for the oracle child")
+        out["cpu_baseline"] = finish_cpu_child(child)
     print(json.dumps(out), flush=True)
 
 

@@ -65,3 +65,19 @@ def test_footprint_bytes():
     p = _lp()
     fb = bench.footprint_bytes(p)
     assert fb == 24 * p.A.nnz + 8 * (p.m + 1) + 8 * (p.n + 1) + 8 * (17 * p.n + 8 * p.m)
+
+
+def test_method_bytes_model_by_hand():
+    """The method's bytes: 24 nnz(A) + 60n + 116m per outer iteration, 32n
+    for a diagonal prox or 12 nnz(P) + 16rn + 92n per inner step, and per
+    check one A^T product (12 nnz(A) + 20n + 8m) and one Q product
+    (12 nnz(P) + 16rn + 16n)."""
+    p = _lp()
+    n, m, z = p.n, p.m, p.A.nnz
+    assert bench.method_bytes_model(p, 7, 0, 3) == 7 * (24 * z + 60 * n + 116 * m + 32 * n) \
+        + 3 * (12 * z + 20 * n + 8 * m + 16 * n)
+    P = sp.csr_matrix(np.eye(n) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1))
+    r = 2
+    q = Problem(n=n, m=m, A=p.A, b=p.b, c=p.c, P=P, R=np.ones((r, n)), D=np.eye(r), cones=p.cones, name="qp")
+    assert bench.method_bytes_model(q, 4, 11, 2) == 4 * (24 * z + 60 * n + 116 * m) \
+        + 11 * (12 * P.nnz + 16 * r * n + 92 * n) + 2 * (12 * z + 20 * n + 8 * m + 12 * P.nnz + 16 * r * n + 16 * n)
