@@ -8,6 +8,12 @@ Cartesian product of blocks from the cone list of the same section: free,
 nonnegative, second-order (v, t), rotated second-order (v, s, t),
 exponential (r, s, t) and 3-D power (x, y, z) with exponent alpha.
 
+The implementation form of the same section (eq. solver-input) is covered
+by the optional fields: row bounds row_lo <= A x <= row_hi (when given they
+replace A x = b; infinite entries are absent bounds, equal entries
+equalities) and box blocks x_i in [x_lo_i, x_hi_i] (blocks of kind "box";
+x_lo / x_hi have length n and are read at the box coordinates only).
+
 The container holds data only; it performs no solver arithmetic.
 """
 from __future__ import annotations
@@ -18,7 +24,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 import scipy.sparse as sp
 
-CONE_TYPES = ("free", "nonneg", "soc", "rsoc", "exp", "pow")
+CONE_TYPES = ("free", "nonneg", "soc", "rsoc", "exp", "pow", "box")
 
 
 @dataclass
@@ -34,6 +40,10 @@ class Problem:
     D: Optional[np.ndarray] = None     # r x r symmetric
     name: str = ""
     meta: dict = field(default_factory=dict)
+    row_lo: Optional[np.ndarray] = None   # m, with row_hi: row_lo <= A x <= row_hi
+    row_hi: Optional[np.ndarray] = None
+    x_lo: Optional[np.ndarray] = None     # n, bounds of the box blocks
+    x_hi: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.A = sp.csr_matrix(self.A, dtype=np.float64)
@@ -43,6 +53,10 @@ class Problem:
         if self.P is not None:
             self.P = sp.csr_matrix(self.P, dtype=np.float64)
             self.P.sort_indices()
+        for f in ("row_lo", "row_hi", "x_lo", "x_hi"):
+            v = getattr(self, f)
+            if v is not None:
+                setattr(self, f, np.ascontiguousarray(v, dtype=np.float64))
         if self.R is not None:
             self.R = np.ascontiguousarray(self.R, dtype=np.float64)
             if self.D is None:
@@ -52,3 +66,7 @@ class Problem:
     @property
     def rank_r(self) -> int:
         return 0 if self.R is None else int(self.R.shape[0])
+
+    @property
+    def has_row_bounds(self) -> bool:
+        return self.row_lo is not None

@@ -696,12 +696,19 @@ class Projector:
     ``project(r, m=None, euclid=None)``: m is the diagonal of M (length n)
     or None (Euclidean).  ``euclid`` is a boolean per block; True selects the
     Euclidean formula (valid when m is constant on the block, since
-    Pi^{cI} = Pi^I)."""
+    Pi^{cI} = Pi^I).  Box blocks [lo_i, hi_i] (the box set of
+    eq. solver-input) clamp, in any diagonal metric; lo and hi have length n
+    and are read at the box coordinates."""
 
-    def __init__(self, cones, n):
+    def __init__(self, cones, n, lo=None, hi=None):
         self.cones = list(cones)
         self.n = n
         self.groups = {}
+        box = [np.arange(st, st + d) for kind, st, d, al in self.cones if kind == "box"]
+        self.box_idx = np.concatenate(box) if box else np.zeros(0, dtype=np.int64)
+        if self.box_idx.size:
+            self.box_lo = np.asarray(lo, dtype=float)[self.box_idx]
+            self.box_hi = np.asarray(hi, dtype=float)[self.box_idx]
         for bi, (kind, st, d, al) in enumerate(self.cones):
             if kind in ("soc", "rsoc"):
                 self.groups.setdefault((kind, d), []).append(bi)
@@ -728,6 +735,8 @@ class Projector:
         out = r.copy()
         if self.nonneg_idx.size:
             out[self.nonneg_idx] = np.maximum(r[self.nonneg_idx], 0.0)
+        if self.box_idx.size:
+            out[self.box_idx] = np.minimum(np.maximum(r[self.box_idx], self.box_lo), self.box_hi)
         if euclid is None:
             euclid = np.ones(len(self.cones), dtype=bool) if m is None else \
                 np.zeros(len(self.cones), dtype=bool)

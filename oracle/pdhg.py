@@ -24,6 +24,12 @@ Passages followed
   eq. practical-restart-rule); defaults of Table practical-defaults.
 * Termination on the unscaled candidate: relative KKT residuals of the
   optimality conditions eq. kkt-cqp.
+* Implementation form (eq. solver-input): row bounds l <= A x <= u and box
+  blocks.  The paper states the form, not the dual step; written from the
+  saddle function with the row constraint A x in B = [l, u], the dual
+  candidate is w_y = sigma (Pi_B(q) - q) with q = A(2 w_x - x) - y/sigma,
+  which is y + sigma (b - A(2 w_x - x)) when l = u = b (equality rows use
+  that form); boxes clamp in the prox.
 
 Readings where the paper is silent (each also listed in the design doc):
 * ||A||_2 by 128 power iterations on A^T A from 1/sqrt(n) (overridable);
@@ -143,21 +149,64 @@ def _is_diagonal(P):
     return bool(np.all(P.row == P.col))
 
 
+def _signed_bound_dot(v, lo, hi):
+    """sum_j (v_j^+ lo_j - v_j^- hi_j), taking only the endpoints that a
+    nonzero part of v selects (the others may be infinite)."""
+    pos = v > 0
+    neg = v < 0
+    return float(v[pos] @ lo[pos]) + float(v[neg] @ hi[neg])
+
+
+def box_dual_part(s, lo, hi):
+    """For box coordinates with bounds lo, hi: lambda = the projection of the
+    reduced cost s onto the set it may take at a solution (R when both
+    bounds are finite, R+ with only lo, R- with only hi, {0} with neither),
+    so dist(s, that set) = |s - lambda|."""
+    lf, hf = np.isfinite(lo), np.isfinite(hi)
+    lam = np.where(lf & hf, s, np.where(lf, np.maximum(s, 0.0),
+                                        np.where(hf, np.minimum(s, 0.0), 0.0)))
+    return lam
+
+
 def kkt_residuals(prob, x, y, proj=None):
-    """Relative KKT residuals of the original problem (eq. kkt-cqp) at (x, y)."""
+    """Relative KKT residuals of the original problem (eq. kkt-cqp) at (x, y).
+
+    With row bounds the primal residual is the distance of A x to [l, u] and
+    the dual objective takes sum(y^+ l - y^- u) in place of <b, y>; on box
+    coordinates the dual residual is the distance of s to the set the
+    reduced cost may take (box_dual_part) and the dual objective gains
+    sum(lambda^+ l^x - lambda^- u^x).  The normaliser of the primal residual
+    is 1 + ||combined bounds|| (||b|| for equalities)."""
+    from .scaling import combined_bounds
     if proj is None:
-        proj = Projector(prob.cones, prob.n)
+        proj = Projector(prob.cones, prob.n, prob.x_lo, prob.x_hi)
     Qx = np.zeros(prob.n)
     if prob.P is not None:
         Qx += prob.P @ x
     if prob.R is not None:
         Qx += prob.R.T @ (prob.D @ (prob.R @ x))
-    rp = float(np.linalg.norm(prob.A @ x - prob.b)) / (1.0 + float(np.linalg.norm(prob.b)))
+    Ax = prob.A @ x
+    if prob.row_lo is None:
+        rpv = Ax - prob.b
+        bnorm = float(np.linalg.norm(prob.b))
+        by = float(prob.b @ y)
+    else:
+        rpv = Ax - np.minimum(np.maximum(Ax, prob.row_lo), prob.row_hi)
+        bnorm = float(np.linalg.norm(combined_bounds(prob.row_lo, prob.row_hi)))
+        by = _signed_bound_dot(y, prob.row_lo, prob.row_hi)
+    rp = float(np.linalg.norm(rpv)) / (1.0 + bnorm)
     s = Qx + prob.c - prob.A.T @ y
-    rd = float(np.linalg.norm(proj.project(-s))) / (1.0 + float(np.linalg.norm(prob.c)))
+    dres = proj.project(-s)
+    boxterm = 0.0
+    if proj.box_idx.size:
+        sb = s[proj.box_idx]
+        lam = box_dual_part(sb, proj.box_lo, proj.box_hi)
+        dres[proj.box_idx] = sb - lam
+        boxterm = _signed_bound_dot(lam, proj.box_lo, proj.box_hi)
+    rd = float(np.linalg.norm(dres)) / (1.0 + float(np.linalg.norm(prob.c)))
     xqx = float(x @ Qx)
     pobj = 0.5 * xqx + float(prob.c @ x)
-    dobj = float(prob.b @ y) - 0.5 * xqx
+    dobj = by + boxterm - 0.5 * xqx
     gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
     return dict(rel_primal=rp, rel_dual=rd, rel_gap=gap, primal_obj=pobj, dual_obj=dobj)
 
@@ -173,6 +222,7 @@ class Setup:
     a_norm: float
     eta: float
     omega0: float
+    kproj: Projector = None     # original-space projector (bounds unscaled) for the checks
 
 
 def setup(prob, st: Settings = None):
@@ -181,7 +231,7 @@ def setup(prob, st: Settings = None):
                        pock_chambolle=st.pock_chambolle,
                        bound_objective=st.bound_objective, enabled=st.scaling)
     q = QOp(sc.P, sc.R, sc.D, prob.n)
-    proj = Projector(prob.cones, prob.n)
+    proj = Projector(prob.cones, prob.n, sc.xlo, sc.xhi)
     euclid_blocks = proj.const_blocks(q.diag)
     a_norm = st.a_norm if st.a_norm > 0 else power_norm(sc.A, st.power_iters)
     if not a_norm > 0:       # A = 0 or no rows: any step size keeps tau sigma ||A||^2 < 1
@@ -194,8 +244,9 @@ def setup(prob, st: Settings = None):
         om = nc / nb
     else:
         om = 1.0
+    kproj = Projector(prob.cones, prob.n, prob.x_lo, prob.x_hi)
     return Setup(prob=prob, st=st, sc=sc, q=q, proj=proj, euclid_blocks=euclid_blocks,
-                 a_norm=a_norm, eta=eta, omega0=om)
+                 a_norm=a_norm, eta=eta, omega0=om, kproj=kproj)
 
 
 # ----------------------------------------------------------------------------
@@ -251,7 +302,14 @@ def pdhg_step(S: Setup, x, y, tau, sigma, eps_in):
     sc = S.sc
     v = x + tau * (sc.A.T @ y)
     wx, nin, _ = prox(S, v, x, tau, eps_in)
-    wy = y + sigma * (sc.b - sc.A @ (2.0 * wx - x))
+    ax = sc.A @ (2.0 * wx - x)
+    if sc.lo is None:
+        wy = y + sigma * (sc.b - ax)
+    else:
+        q = ax - y / sigma
+        wy = sigma * (np.minimum(np.maximum(q, sc.lo), sc.hi) - q)
+        eq = sc.lo == sc.hi
+        wy[eq] = y[eq] + sigma * (sc.lo[eq] - ax[eq])
     return wx, wy, nin
 
 
@@ -322,7 +380,7 @@ def solve(prob, st: Settings = None, x0=None, y0=None, S: Setup = None):
                           (E <= st.beta_n * E0 and E > Eprev) or \
                           (k + 1 >= st.beta_a * ktot)
             Eprev = E
-            kkt = kkt_residuals(prob, sc.unscale_x(wx), sc.unscale_y(wy), S.proj)
+            kkt = kkt_residuals(prob, sc.unscale_x(wx), sc.unscale_y(wy), S.kproj)
         if len(trace) < st.trace_iters:
             trace.append(dict(x=x.copy(), y=y.copy(), wx=wx.copy(), wy=wy.copy(),
                               tau=tau, sigma=sigma, omega=omega, inner=nin,
@@ -356,7 +414,7 @@ def solve(prob, st: Settings = None, x0=None, y0=None, S: Setup = None):
             x, y = xn, yn
             k += 1
     if kkt is None or status == "MAX_ITER":
-        kkt = kkt_residuals(prob, sc.unscale_x(wx), sc.unscale_y(wy), S.proj)
+        kkt = kkt_residuals(prob, sc.unscale_x(wx), sc.unscale_y(wy), S.kproj)
     return Result(status=status, iterations=ktot, inner_iterations=inner_tot,
                   restarts=restarts, x=sc.unscale_x(wx), y=sc.unscale_y(wy), kkt=kkt,
                   solve_s=time.perf_counter() - t0, trace=trace, omega=omega,
@@ -401,7 +459,7 @@ def _solve_avg(S: Setup, x0, y0):
                 break
         x, y = xb.copy(), yb.copy()
         restarts += 1
-        kkt = kkt_residuals(prob, sc.unscale_x(xb), sc.unscale_y(yb), S.proj)
+        kkt = kkt_residuals(prob, sc.unscale_x(xb), sc.unscale_y(yb), S.kproj)
         if max(kkt["rel_primal"], kkt["rel_dual"], kkt["rel_gap"]) <= st.tol:
             status = "OPTIMAL"
             break

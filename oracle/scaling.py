@@ -24,6 +24,14 @@ With x~ = S_x x, A~ = S_y A S_x^-1, Q~ = S_x^-1 Q S_x^-1, c~ = S_x^-1 c,
 b~ = S_y b; an original solution is recovered as x = nu_b S_x^-1 x^,
 y = nu_c S_y y^.
 
+Implementation form (eq. solver-input): row bounds scale with their rows,
+l~ = S_y l, u~ = S_y u, box bounds with their coordinates, l^x~ = S_x l^x,
+and both are divided by nu_b with b; box coordinates take coordinatewise
+factors like R+ and free ones.  With row bounds, nu_b is built from the
+combined bound of each row (its value for an equality, else the larger
+finite endpoint in magnitude, 0 when neither is finite): "the bound data" of
+the bound-objective rescaling.
+
 Pins: hand-derived worked examples of one and two Ruiz passes, of a
 Pock-Chambolle pass with alpha = 1 and alpha = 2, of Ruiz followed by
 Pock-Chambolle and of the bound-objective constants
@@ -53,6 +61,10 @@ class Scaled:
     Sy: np.ndarray
     nu_b: float
     nu_c: float
+    lo: Optional[np.ndarray] = None    # scaled row bounds (None: A x = b)
+    hi: Optional[np.ndarray] = None
+    xlo: Optional[np.ndarray] = None   # scaled box bounds (length n)
+    xhi: Optional[np.ndarray] = None
 
     def unscale_x(self, xh):
         return self.nu_b * xh / self.Sx
@@ -68,7 +80,15 @@ class Scaled:
 
 
 def _cone_blocks(cones):
-    return [(st, d) for kind, st, d, al in cones if kind not in ("free", "nonneg")]
+    return [(st, d) for kind, st, d, al in cones if kind not in ("free", "nonneg", "box")]
+
+
+def combined_bounds(lo, hi):
+    """Per row: the value of an equality, else the larger finite endpoint in
+    magnitude (0 when neither endpoint is finite)."""
+    flo = np.where(np.isfinite(lo), np.abs(lo), 0.0)
+    fhi = np.where(np.isfinite(hi), np.abs(hi), 0.0)
+    return np.where(lo == hi, lo, np.maximum(flo, fhi))
 
 
 def _apply(A, row, col):
@@ -114,6 +134,14 @@ def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
             Sx = Sx * col
     c = prob.c / Sx
     b = prob.b * Sy
+    lo = hi = xlo = xhi = None
+    if prob.row_lo is not None:
+        lo = prob.row_lo * Sy
+        hi = prob.row_hi * Sy
+        b = combined_bounds(lo, hi)
+    if prob.x_lo is not None:
+        xlo = prob.x_lo * Sx
+        xhi = prob.x_hi * Sx
     P = None
     if prob.P is not None:
         P = (sp.diags(1.0 / Sx) @ prob.P @ sp.diags(1.0 / Sx)).tocsr()
@@ -125,9 +153,14 @@ def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
         nu_c = float(np.linalg.norm(c)) + 1.0
     b = b / nu_b
     c = c / nu_c
+    if lo is not None:
+        lo, hi = lo / nu_b, hi / nu_b
+    if xlo is not None:
+        xlo, xhi = xlo / nu_b, xhi / nu_b
     if P is not None:
         P = (P * (nu_b / nu_c)).tocsr()
     if D is not None:
         D = D * (nu_b / nu_c)
     A.sort_indices()
-    return Scaled(A=A, b=b, c=c, P=P, R=R, D=D, Sx=Sx, Sy=Sy, nu_b=nu_b, nu_c=nu_c)
+    return Scaled(A=A, b=b, c=c, P=P, R=R, D=D, Sx=Sx, Sy=Sy, nu_b=nu_b, nu_c=nu_c,
+                  lo=lo, hi=hi, xlo=xlo, xhi=xhi)
