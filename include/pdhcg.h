@@ -8,6 +8,9 @@
  * (v, t), rotated second-order (v, s, t), exponential (r, s, t) and 3-D power
  * (x, y, z; exponent alpha) blocks (implementation section, cone list).
  *
+ * The implementation form of the same section (eq. solver-input) is also
+ * accepted: two-sided row bounds l <= A x <= u and box blocks [l^x, u^x].
+ *
  * Method (implementation section): primal-first PDHG operator whose primal
  * step is the conic proximal subproblem (eq. prox-subproblem), solved by one
  * diagonal-metric projection when Q is diagonal (eq. diagonal-q-metric) or by
@@ -70,6 +73,9 @@ extern "C" {
 #define PDHCG_CONE_EXP    4   /* (r, s, t): cl{s > 0, s e^{r/s} <= t}, dim 3  */
 #define PDHCG_CONE_POW    5   /* (x, y, z): x^a y^(1-a) >= |z|, dim 3,
                                  alpha in (0, 1)                              */
+#define PDHCG_CONE_BOX    6   /* x_i in [x_lo_i, x_hi_i] on each coordinate of
+                                 the block (the box set of eq. solver-input;
+                                 bounds from pdhcg_problem.x_lo / x_hi)      */
 
 /* ---- enumerations in settings ---------------------------------------- */
 #define PDHCG_SCHEME_RH   0   /* reflected-Halpern epochs (eq. rh-update)     */
@@ -107,6 +113,18 @@ typedef struct {
     const int32_t* cone_start;
     const int32_t* cone_dim;
     const double*  cone_alpha;    /* read for POW blocks only; nullable       */
+    /* implementation form (eq. solver-input), all nullable:
+     * row_lo, row_hi (m): row_lo <= A x <= row_hi replaces A x = b (b may
+     *   then be NULL); -INFINITY / +INFINITY mark absent endpoints, equal
+     *   endpoints an equality; both or neither must be given;
+     * x_lo, x_hi (n): bounds of the coordinates of PDHCG_CONE_BOX blocks
+     *   (read there only; required when such a block exists).
+     * Invalid: NaN, lo > hi, a lower endpoint +INFINITY or an upper
+     * endpoint -INFINITY (PDHCG_E_ARG).                                      */
+    const double*  row_lo;
+    const double*  row_hi;
+    const double*  x_lo;
+    const double*  x_hi;
 } pdhcg_problem;
 
 typedef struct {

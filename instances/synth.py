@@ -18,6 +18,9 @@ fisher           quasilinear Fisher market in exponential-cone form
                  (Section "Large-Scale Fisher Equilibrium", eq. fisher-conic).
 tiny_free_qp / tiny_nonneg_qp / tiny_mixed
                  small families for whole-solve pins.
+bounded_qp       the implementation form: two-sided, one-sided, equality
+                 and free rows, box coordinates with finite and one-sided
+                 bounds, with R+, free, SOC and EXP blocks.
 """
 from __future__ import annotations
 
@@ -378,3 +381,62 @@ def tiny_mixed(seed=0, m=12, with_q=True, lowrank=True):
             D = np.eye(2)
     return Problem(n=n, m=m, A=A, b=b, c=c, P=P, R=R, D=D, cones=cones,
                    name=f"tiny_mixed[{seed}]", meta={"x_feas": x0})
+
+
+# ----------------------------------------------------------------------------
+# implementation form: row bounds and box blocks
+# ----------------------------------------------------------------------------
+def bounded_qp(seed=0, n_box=40, n_cone_soc=2, n_exp=1, m=30, density=0.2, q="lowrank"):
+    """Rows l <= A x <= u of five kinds around a strictly interior point
+    (range, equality, lower only, upper only, free, in a seeded mix); box
+    coordinates with finite, lower-only and upper-only bounds; a nonnegative
+    block, a free block, SOC(5) blocks and EXP blocks.  q: None (Q = 0),
+    "diag" or "lowrank" (diag + rank-2 factor).  Costs on the coordinates
+    that are unbounded in one direction point towards the bound."""
+    rng = np.random.default_rng(seed)
+    cones = []
+    st = 0
+    cones.append(("box", st, n_box, 0.0)); st += n_box
+    cones.append(("nonneg", st, 6, 0.0)); st += 6
+    cones.append(("free", st, 3, 0.0)); st += 3
+    for _ in range(n_cone_soc):
+        cones.append(("soc", st, 5, 0.0)); st += 5
+    for _ in range(n_exp):
+        cones.append(("exp", st, 3, 0.0)); st += 3
+    n = st
+    A = sp.random(m, n, density=density, random_state=rng, data_rvs=rng.standard_normal, format="csr")
+    # every free coordinate appears in an equality or two-sided row
+    A = (A + sp.csr_matrix((np.ones(3), ([0, 1, 2], [n_box + 6, n_box + 7, n_box + 8])), shape=(m, n))).tocsr()
+    x0 = _interior_point(rng, n, cones)
+    x0[:n_box] = rng.uniform(0.2, 0.8, n_box)
+    ax = A @ x0
+    kinds = rng.choice(["range", "eq", "lo", "hi", "free"], size=m, p=[0.4, 0.2, 0.15, 0.15, 0.1])
+    kinds[:3] = ["eq", "range", "eq"]
+    lo = np.empty(m)
+    hi = np.empty(m)
+    for j, k in enumerate(kinds):
+        a, b = rng.uniform(0.05, 1.0, 2)
+        lo[j], hi[j] = {"range": (ax[j] - a, ax[j] + b), "eq": (ax[j], ax[j]), "lo": (ax[j] - a, np.inf),
+                        "hi": (-np.inf, ax[j] + b), "free": (-np.inf, np.inf)}[k]
+    xlo = np.full(n, -np.inf)
+    xhi = np.full(n, np.inf)
+    third = n_box // 3
+    xlo[:n_box] = x0[:n_box] - rng.uniform(0.1, 0.6, n_box)
+    xhi[:third] = x0[:third] + rng.uniform(0.1, 0.6, third)            # finite box
+    # [third, 2 third): lower only; [2 third, n_box): upper only
+    xhi[2 * third:n_box] = x0[2 * third:n_box] + rng.uniform(0.1, 0.6, n_box - 2 * third)
+    xlo[2 * third:n_box] = -np.inf
+    c = rng.standard_normal(n)
+    c[third:2 * third] = np.abs(c[third:2 * third]) + 0.1
+    c[2 * third:n_box] = -np.abs(c[2 * third:n_box]) - 0.1
+    c[n_box:n_box + 6] = np.abs(c[n_box:n_box + 6]) + 0.1
+    P = R = D = None
+    if q in ("diag", "lowrank"):
+        P = sp.diags(rng.uniform(0.1, 1.0, size=n)).tocsr()
+    if q == "lowrank":
+        R = rng.standard_normal((2, n)) / math.sqrt(n)
+        D = np.eye(2)
+    b = np.where(lo == hi, lo, 0.0)
+    return Problem(n=n, m=m, A=A, b=b, c=c, P=P, R=R, D=D, cones=cones, row_lo=lo, row_hi=hi,
+                   x_lo=xlo, x_hi=xhi, name=f"bounded_qp[{seed},n={n},m={m},q={q}]",
+                   meta={"x_feas": x0, "row_kinds": kinds})

@@ -35,7 +35,8 @@ Readings where the paper is silent (each also listed in the design doc):
 * ||A||_2 by 128 power iterations on A^T A from 1/sqrt(n) (overridable);
   a zero estimate (A = 0 or no rows) is replaced by 1;
 * omega_0 = ||c^||/||b^|| when both exceed 1e-10, else 1 (overridable);
-* start z = (Pi_K(x0^), y0^) or zero; the inner solve starts at the Halpern
+* start z = (Pi_X(x0^), y0^), x0^ = 0 without a warm start (0 lies in every
+  cone but not necessarily in a box); the inner solve starts at the Halpern
   primal state x; first inner step uses alpha = 1 (Jacobi) or
   1/max(diag Q^ + 1/tau) (Euclidean); J_max = 500;
 * checks at k = 0 of each epoch (defines E_0), whenever the global
@@ -340,7 +341,7 @@ def solve(prob, st: Settings = None, x0=None, y0=None, S: Setup = None):
     sc = S.sc
     t0 = time.perf_counter()
     n, m = prob.n, prob.m
-    x = S.proj.project(sc.scale_x(x0)) if x0 is not None else np.zeros(n)
+    x = S.proj.project(sc.scale_x(x0) if x0 is not None else np.zeros(n))
     y = sc.scale_y(y0) if y0 is not None else np.zeros(m)
     ax, ay = x.copy(), y.copy()
     k = 0
@@ -428,7 +429,7 @@ def _solve_avg(S: Setup, x0, y0):
     rule, driven by the movement of consecutive PDHG iterates."""
     st, sc, prob = S.st, S.sc, S.prob
     t0 = time.perf_counter()
-    x = S.proj.project(sc.scale_x(x0)) if x0 is not None else np.zeros(prob.n)
+    x = S.proj.project(sc.scale_x(x0) if x0 is not None else np.zeros(prob.n))
     y = sc.scale_y(y0) if y0 is not None else np.zeros(prob.m)
     tau = S.eta / S.omega0
     sigma = S.eta * S.omega0

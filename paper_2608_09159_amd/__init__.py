@@ -24,7 +24,8 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
 
 ``problem`` is any object with the fields of ``instances.Problem``
 (n, m, A as scipy CSR, b, c, optional P / R / D, cones as
-(type, start, dim, alpha) tuples with type in CONE_CODES).
+(type, start, dim, alpha) tuples with type in CONE_CODES, optional row
+bounds row_lo / row_hi and box bounds x_lo / x_hi).
 """
 from __future__ import annotations
 
@@ -36,7 +37,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdhcg.so")
 
-CONE_CODES = {"free": 0, "nonneg": 1, "soc": 2, "rsoc": 3, "exp": 4, "pow": 5}
+CONE_CODES = {"free": 0, "nonneg": 1, "soc": 2, "rsoc": 3, "exp": 4, "pow": 5, "box": 6}
 STATUS = {1: "OPTIMAL", 2: "MAX_ITER", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "ABORTED"}
 SCHEMES = {"rh": 0, "avg": 1}
 INNER = {"jacobi": 0, "euclid": 1}
@@ -54,7 +55,8 @@ class ProblemC(C.Structure):
                 ("P_rowptr", _i64p), ("P_col", _i32p), ("P_val", _dp),
                 ("r", C.c_int32), ("R", _dp), ("D", _dp),
                 ("nblocks", C.c_int32), ("cone_type", _i32p), ("cone_start", _i32p),
-                ("cone_dim", _i32p), ("cone_alpha", _dp)]
+                ("cone_dim", _i32p), ("cone_alpha", _dp),
+                ("row_lo", _dp), ("row_hi", _dp), ("x_lo", _dp), ("x_hi", _dp)]
 
 
 class Settings(C.Structure):
@@ -225,6 +227,12 @@ class _Marshalled:
         pc.cone_start = _ptr(arr([s for _, s, _, _ in prob.cones], np.int32), C.c_int32)
         pc.cone_dim = _ptr(arr([d for _, _, d, _ in prob.cones], np.int32), C.c_int32)
         pc.cone_alpha = _ptr(arr([a for _, _, _, a in prob.cones], np.float64), C.c_double)
+        if getattr(prob, "row_lo", None) is not None:
+            pc.row_lo = _ptr(arr(prob.row_lo, np.float64), C.c_double)
+            pc.row_hi = _ptr(arr(prob.row_hi, np.float64), C.c_double)
+        if getattr(prob, "x_lo", None) is not None:
+            pc.x_lo = _ptr(arr(prob.x_lo, np.float64), C.c_double)
+            pc.x_hi = _ptr(arr(prob.x_hi, np.float64), C.c_double)
         self.pc = pc
 
 

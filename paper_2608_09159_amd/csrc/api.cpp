@@ -234,6 +234,10 @@ int upload_instance(Handle* h, Instance* I) {
   P.norm_b = H.norm_b;
   P.norm_c = H.norm_c;
   P.q_diag = H.q_diag ? 1 : 0;
+  P.rlo = H.rlo.empty() ? nullptr : B.upload(H.rlo);
+  P.rhi = H.rhi.empty() ? nullptr : B.upload(H.rhi);
+  P.xlo = H.xlo.empty() ? nullptr : B.upload(H.xlo);
+  P.xhi = H.xhi.empty() ? nullptr : B.upload(H.xhi);
   I->qmax = 0.0;
   for (double q : H.qdiag) I->qmax = std::max(I->qmax, q);
 
@@ -418,7 +422,7 @@ int upload_instance(Handle* h, Instance* I) {
         if (H.P.rows > 0 && !H.p_diag) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
         return w;
       };
-      if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
+      if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG || cb.type == PDHCG_CONE_BOX) {
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
           cu.emplace_back(i + 1, wcoord(i));
           cheavy.push_back(rownz(i) > heavy_nz);
@@ -756,6 +760,10 @@ void carve_instance(const HostInstance& H, int trace_cap, bool avg, Carve& c, In
   P.norm_b = H.norm_b;
   P.norm_c = H.norm_c;
   P.q_diag = H.q_diag ? 1 : 0;
+  P.rlo = H.rlo.empty() ? nullptr : c.put(H.rlo);
+  P.rhi = H.rhi.empty() ? nullptr : c.put(H.rhi);
+  P.xlo = H.xlo.empty() ? nullptr : c.put(H.xlo);
+  P.xhi = H.xhi.empty() ? nullptr : c.put(H.xhi);
   DevVec& V = D.V;
   V = DevVec{};
   V.x = c.take<double>(n);
@@ -1429,7 +1437,7 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count) {
 
 int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha, const double* r,
                         const double* metric, double* out) {
-  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;
+  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;   // no BOX
   if ((type == PDHCG_CONE_RSOC && dim < 2) ||
       ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) && dim != 3))
     return PDHCG_E_CONE;

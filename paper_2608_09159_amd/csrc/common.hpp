@@ -10,7 +10,7 @@ constexpr int RMAX = 32;          // largest supported rank of the dense factor 
 constexpr int MAX_BLOCK = 1024;
 
 // per-coordinate kind used by elementwise passes
-enum : uint8_t { CT_FREE = 0, CT_NONNEG = 1, CT_CONE = 2 };
+enum : uint8_t { CT_FREE = 0, CT_NONNEG = 1, CT_CONE = 2, CT_BOX = 3 };
 
 // reduction slots (each slot holds one double per workgroup)
 enum Slot : int {
@@ -31,6 +31,7 @@ enum Slot : int {
   SL_MOVY2,        // ||w_y - a_y||^2
   SL_NAN,          // count of non-finite values
   SL_SPS,          // <s, P s>, diagonal P          (one-sync inner step)
+  SL_BOXD,         // sum(lambda+ l^x - lambda- u^x) over box coordinates (scaled)
   SL_H0,           // R u : RMAX slots
   SL_HS0 = SL_H0 + RMAX,   // R s : RMAX slots (one-sync inner step)
   SL_COUNT = SL_HS0 + RMAX
@@ -48,7 +49,11 @@ struct DevProblem {
   // FP32 copies of the values of A, A^T, P, R (FP32 mode only; else null)
   const float* A_valf; const float* AT_valf; const float* P_valf; const float* Rf;
   const double* Dm;      // r x r (scaled)
-  const double* b;       // m (scaled)
+  const double* b;       // m (scaled; the combined row bounds when rows are bounded)
+  const double* rlo;     // m scaled row bounds (nullable: A x = b)
+  const double* rhi;
+  const double* xlo;     // n scaled box bounds (nullable: no box block)
+  const double* xhi;
   const double* c;       // n (scaled)
   const double* qd;      // n diag(Q^)
   const double* Sx;      // n

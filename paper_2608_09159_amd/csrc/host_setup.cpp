@@ -97,7 +97,7 @@ void interleave(HostInstance& H) {
   struct Unit { int start, dim, type; double alpha; double key; };
   std::vector<Unit> plain, cone;
   for (const auto& cb : H.cones) {
-    if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG) {
+    if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG || cb.type == PDHCG_CONE_BOX) {
       for (int i = cb.start; i < cb.start + cb.dim; ++i) plain.push_back({i, 1, cb.type, 0.0, 0.0});
     } else {
       cone.push_back({cb.start, cb.dim, cb.type, cb.alpha, 0.0});
@@ -123,7 +123,7 @@ void interleave(HostInstance& H) {
   for (const auto& u : all) {
     const int ns = (int)perm.size();
     for (int j = 0; j < u.dim; ++j) perm.push_back(u.start + j);
-    const bool elem = u.type == PDHCG_CONE_FREE || u.type == PDHCG_CONE_NONNEG;
+    const bool elem = u.type == PDHCG_CONE_FREE || u.type == PDHCG_CONE_NONNEG || u.type == PDHCG_CONE_BOX;
     if (elem && !cones.empty() && cones.back().type == u.type && cones.back().start + cones.back().dim == ns)
       cones.back().dim += 1;
     else
@@ -188,6 +188,15 @@ void interleave(HostInstance& H) {
   }
   H.c.swap(c2);
   H.Sx.swap(s2);
+  if (!H.xlo.empty()) {
+    std::vector<double> l2(n), h2(n);
+    for (int j = 0; j < n; ++j) {
+      l2[j] = H.xlo[perm[j]];
+      h2[j] = H.xhi[perm[j]];
+    }
+    H.xlo.swap(l2);
+    H.xhi.swap(h2);
+  }
   H.cones.swap(cones);
   H.perm.swap(perm);
 }
@@ -203,7 +212,9 @@ void apply_scaling(Csr& a, const std::vector<double>& row, const std::vector<dou
 int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance& H) {
   if (p.n < 1 || p.m < 0 || p.r < 0) return PDHCG_E_SHAPE;
   if (p.r > RMAX) return PDHCG_E_SHAPE;
-  if (!p.c || (p.m > 0 && (!p.b || !p.A_rowptr))) return PDHCG_E_ARG;
+  const bool row_bounds = p.row_lo != nullptr || p.row_hi != nullptr;
+  if (row_bounds && (!p.row_lo || !p.row_hi)) return PDHCG_E_ARG;
+  if (!p.c || (p.m > 0 && ((!p.b && !row_bounds) || !p.A_rowptr))) return PDHCG_E_ARG;
   if (p.nblocks < 1 || !p.cone_type || !p.cone_start || !p.cone_dim) return PDHCG_E_CONE;
   const int n = p.n, m = p.m;
   H.n = n;
@@ -220,6 +231,14 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
       case PDHCG_CONE_FREE:
       case PDHCG_CONE_NONNEG:
       case PDHCG_CONE_SOC:
+        break;
+      case PDHCG_CONE_BOX:
+        if (!p.x_lo || !p.x_hi) return PDHCG_E_ARG;
+        for (int i = cb.start; i < cb.start + cb.dim; ++i) {
+          const double lo = p.x_lo[i], hi = p.x_hi[i];
+          if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY || hi == -INFINITY)
+            return PDHCG_E_ARG;
+        }
         break;
       case PDHCG_CONE_RSOC:
         if (cb.dim < 2) return PDHCG_E_CONE;
@@ -271,10 +290,39 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
       for (int a = 0; a < r; ++a) H.D[a * r + a] = 1.0;
     }
   }
-  H.b.assign(p.b ? p.b : nullptr, p.b ? p.b + m : nullptr);
   H.c.assign(p.c, p.c + n);
-  for (double v : H.b) if (!std::isfinite(v)) return PDHCG_E_ARG;
   for (double v : H.c) if (!std::isfinite(v)) return PDHCG_E_ARG;
+  H.rlo.clear(); H.rhi.clear(); H.xlo.clear(); H.xhi.clear();
+  if (row_bounds) {
+    // b holds the combined bound of each row: its value for an equality,
+    // else the finite endpoint of larger magnitude (0 when neither is
+    // finite); it sets the residual normaliser, nu_b and omega_0
+    H.rlo.assign(p.row_lo, p.row_lo + m);
+    H.rhi.assign(p.row_hi, p.row_hi + m);
+    H.b.assign(m, 0.0);
+    for (int l = 0; l < m; ++l) {
+      const double lo = H.rlo[l], hi = H.rhi[l];
+      if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY || hi == -INFINITY) return PDHCG_E_ARG;
+      if (lo == hi) H.b[l] = lo;
+      else H.b[l] = std::max(std::isfinite(lo) ? std::fabs(lo) : 0.0, std::isfinite(hi) ? std::fabs(hi) : 0.0);
+    }
+  } else {
+    H.b.assign(p.b ? p.b : nullptr, p.b ? p.b + m : nullptr);
+    for (double v : H.b) if (!std::isfinite(v)) return PDHCG_E_ARG;
+  }
+  bool has_box = false;
+  for (const auto& cb : H.cones) has_box = has_box || cb.type == PDHCG_CONE_BOX;
+  if (has_box) {
+    // box bounds per coordinate (unused outside box blocks)
+    H.xlo.assign(n, -INFINITY);
+    H.xhi.assign(n, INFINITY);
+    for (const auto& cb : H.cones)
+      if (cb.type == PDHCG_CONE_BOX)
+        for (int i = cb.start; i < cb.start + cb.dim; ++i) {
+          H.xlo[i] = p.x_lo[i];
+          H.xhi[i] = p.x_hi[i];
+        }
+  }
   H.norm_b = norm2(H.b);
   H.norm_c = norm2(H.c);
 
@@ -283,7 +331,8 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   H.Sy.assign(m, 1.0);
   std::vector<std::pair<int, int>> blocks;  // non-elementwise cone blocks
   for (const auto& cb : H.cones)
-    if (cb.type != PDHCG_CONE_FREE && cb.type != PDHCG_CONE_NONNEG) blocks.emplace_back(cb.start, cb.dim);
+    if (cb.type != PDHCG_CONE_FREE && cb.type != PDHCG_CONE_NONNEG && cb.type != PDHCG_CONE_BOX)
+      blocks.emplace_back(cb.start, cb.dim);
   Csr& A = H.A;
   if (s.scaling) {
     std::vector<double> row(m), col(n);
@@ -338,6 +387,14 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   // c~ = S_x^-1 c, b~ = S_y b, P~ = S_x^-1 P S_x^-1, R~ = R S_x^-1
   for (int i = 0; i < n; ++i) H.c[i] /= H.Sx[i];
   for (int l = 0; l < m; ++l) H.b[l] *= H.Sy[l];
+  for (size_t l = 0; l < H.rlo.size(); ++l) {
+    H.rlo[l] *= H.Sy[l];   // infinite endpoints stay infinite
+    H.rhi[l] *= H.Sy[l];
+  }
+  for (size_t i = 0; i < H.xlo.size(); ++i) {
+    H.xlo[i] *= H.Sx[i];
+    H.xhi[i] *= H.Sx[i];
+  }
   if (hasP)
     for (int64_t i = 0; i < n; ++i)
       for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k)
@@ -351,6 +408,10 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   }
   for (auto& v : H.b) v /= H.nu_b;
   for (auto& v : H.c) v /= H.nu_c;
+  for (auto& v : H.rlo) v /= H.nu_b;
+  for (auto& v : H.rhi) v /= H.nu_b;
+  for (auto& v : H.xlo) v /= H.nu_b;
+  for (auto& v : H.xhi) v /= H.nu_b;
   const double qs = H.nu_b / H.nu_c;
   for (auto& v : H.P.val) v *= qs;
   for (auto& v : H.D) v *= qs;
@@ -397,6 +458,9 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
         break;
       case PDHCG_CONE_NONNEG:
         for (int i = cb.start; i < cb.start + cb.dim; ++i) H.ctype[i] = CT_NONNEG;
+        break;
+      case PDHCG_CONE_BOX:
+        for (int i = cb.start; i < cb.start + cb.dim; ++i) H.ctype[i] = CT_BOX;
         break;
       case PDHCG_CONE_SOC:
       case PDHCG_CONE_RSOC:

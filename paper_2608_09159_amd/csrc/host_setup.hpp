@@ -26,7 +26,10 @@ struct HostInstance {
   int n = 0, m = 0, r = 0;
   Csr A, AT, P;             // scaled A^, its transpose, scaled P^ (rows==0: absent)
   std::vector<double> R, D; // scaled R^ (r x n) and D^ (r x r)
-  std::vector<double> b, c; // scaled
+  std::vector<double> b, c; // scaled (b: the combined row bounds when rows are bounded)
+  // implementation form: scaled row bounds (empty: A x = b) and scaled box
+  // bounds per coordinate (empty: no box block)
+  std::vector<double> rlo, rhi, xlo, xhi;
   std::vector<double> Sx, Sy, qdiag;
   double nu_b = 1, nu_c = 1;
   double norm_b = 0, norm_c = 0;  // of the original data

@@ -480,6 +480,48 @@ __device__ __forceinline__ double elem_proj(uint8_t ct, double z) {
   return ct == CT_NONNEG ? fmax(z, 0.0) : z;
 }
 
+// elementwise projection of coordinate i, box blocks included (a clamp to
+// [l^x_i, u^x_i], the same in every diagonal metric)
+__device__ __forceinline__ double elem_proj_i(const DevProblem& P, long i, uint8_t ct, double z) {
+  return ct == CT_BOX ? fmin(fmax(z, P.xlo[i]), P.xhi[i]) : elem_proj(ct, z);
+}
+
+// dual candidate of row l from y_l and (A xbar)_l, xbar = 2 w_x - x
+// (eq. theory-pdhg-map): y + sigma (b - A xbar) for an equality row; with
+// row bounds l <= A x <= u, the proximal step of the saddle function's row
+// term, sigma (Pi_[l,u](q) - q) with q = A xbar - y/sigma
+__device__ __forceinline__ double dual_candidate(const DevProblem& P, long l, double yl, double axb,
+                                                 double sigma) {
+  if (P.rlo) {
+    const double lo = P.rlo[l], hi = P.rhi[l];
+    if (lo != hi) {
+      const double q = axb - yl / sigma;
+      return sigma * (fmin(fmax(q, lo), hi) - q);
+    }
+  }
+  return yl + sigma * (P.b[l] - axb);
+}
+
+// (A x)_l minus its nearest point of the row's bounds (scaled)
+__device__ __forceinline__ double row_residual(const DevProblem& P, long l, double ax) {
+  return P.rlo ? ax - fmin(fmax(ax, P.rlo[l]), P.rhi[l]) : ax - P.b[l];
+}
+
+// the row's term of the dual objective: b_l y_l, or with bounds
+// y^+ l - y^- u (the endpoint the sign of y selects)
+__device__ __forceinline__ double row_dual_term(const DevProblem& P, long l, double y) {
+  if (!P.rlo) return P.b[l] * y;
+  return y > 0.0 ? y * P.rlo[l] : (y < 0.0 ? y * P.rhi[l] : 0.0);
+}
+
+// on a box coordinate with bounds lo, hi: the set the reduced cost may take
+// at a solution (R with both bounds finite, R+ with only lo, R- with only
+// hi, {0} with neither), and the projection of v onto it
+__device__ __forceinline__ double box_dual_proj(double lo, double hi, double v) {
+  const bool lf = isfinite(lo), hf = isfinite(hi);
+  return (lf && hf) ? v : (lf ? fmax(v, 0.0) : (hf ? fmin(v, 0.0) : 0.0));
+}
+
 // matrix values of the bulk sweeps (A^T y, P u, R u, A w off check
 // iterations): the FP64 data or, in FP32 mode, their FP32 copies
 template <class MV>
@@ -755,7 +797,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if constexpr (SOLO) hw_clear(L);
     for_range(c0, c1, [&](long i, bool act) {
       bool el = act && P.ctype[i] != CT_CONE;
-      double x = el ? elem_proj(P.ctype[i], V.zb[i]) : 0.0;
+      double x = el ? elem_proj_i(P, i, P.ctype[i], V.zb[i]) : 0.0;
       if (el) { V.x[i] = x; V.ax[i] = x; }
       if constexpr (SOLO) hw_add(L, R64, r, i, x, el);
     });
@@ -815,7 +857,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, X, V.t2, c0, c1, La);
     if (!P.q_diag) make_ht(L, P, hX);
     else __syncthreads();
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     for_range(c0, c1, [&](long i, bool act) {
       if (!act) return;
       const double wi = X[i];
@@ -832,6 +874,14 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       const uint8_t ct = P.ctype[i];
       if (ct == CT_FREE) acc[1] += so * so;
       else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
+      else if (ct == CT_BOX) {
+        // distance of s to the reduced cost's set, and lambda^+ l - lambda^- u
+        const double lo = P.xlo[i], hi = P.xhi[i];
+        const double t = so - box_dual_proj(lo, hi, so);
+        acc[1] += t * t;
+        const double lam = box_dual_proj(lo, hi, si);
+        acc[2] += lam > 0.0 ? lam * lo : (lam < 0.0 ? lam * hi : 0.0);   // SL_BOXD
+      }
       else V.s[i] = si;
     });
     if (has_items) {
@@ -845,8 +895,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         }
       });
     }
-    const int sl[2] = {SL_XQX, SL_RD2};
-    block_store(L, acc, sl, 2, part, G, rank);
+    const int sl[3] = {SL_XQX, SL_RD2, SL_BOXD};
+    block_store(L, acc, sl, 3, part, G, rank);
   };
 
   // residuals, objectives and status from the reduced slots SL_RP2, SL_RD2,
@@ -857,7 +907,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     C.rel_p = sqrt(sc[SL_RP2]) / (1.0 + P.norm_b);
     C.rel_d = sqrt(sc[SL_RD2]) / (1.0 + P.norm_c);
     C.pobj = scale * (0.5 * sc[SL_XQX] + sc[SL_CX]);
-    C.dobj = scale * (sc[SL_BY] - 0.5 * sc[SL_XQX]);
+    C.dobj = scale * (sc[SL_BY] + sc[SL_BOXD] - 0.5 * sc[SL_XQX]);
     C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
     if (bad || !isfinite(C.rel_p) || !isfinite(C.rel_d) || !isfinite(C.rel_gap)) {
       C.status = PDHCG_NUMERICAL;
@@ -904,7 +954,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         const double vi = V.x[i] + tau * V.t1[i];
         const double mi = 1.0 + tau * P.qd[i];
         const double z = (vi - tau * P.c[i]) / mi;
-        if (P.ctype[i] != CT_CONE) V.wx[i] = elem_proj(P.ctype[i], z);
+        if (P.ctype[i] != CT_CONE) V.wx[i] = elem_proj_i(P, i, P.ctype[i], z);
         else V.zb[i] = z;
       });
       if (has_items) {
@@ -932,7 +982,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           V.up[i] = xi;
           if (P.ctype[i] != CT_CONE) {
             el = true;
-            un = elem_proj(P.ctype[i], z);
+            un = elem_proj_i(P, i, P.ctype[i], z);
             V.u[i] = un;
             const double si = un - xi;
             acc[0] += si * si;
@@ -1050,7 +1100,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             }
             if (el) {
               const double mi = Mq(i);
-              un = elem_proj(P.ctype[i], ui - alpha * gi / mi);
+              un = elem_proj_i(P, i, P.ctype[i], ui - alpha * gi / mi);
               const double si = un - ui;
               acc[0] += si * si;
               if (fuse) {
@@ -1121,7 +1171,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         const double aw = spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
-          const double wy = yl + sigma * (P.b[l] - (2.0 * aw - axl));
+          const double wy = dual_candidate(P, l, yl, 2.0 * aw - axl, sigma);
           V.wy[l] = wy;
           V.Aw[l] = aw;
           if (tracing) TB.wy[L.C.ktot * m + l] = wy;
@@ -1132,9 +1182,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           if (ep_end) {
             V.y[l] = yb;
             V.Ax[l] = axb;
-            const double rp = P.nu_b * (axb - P.b[l]) / P.Sy[l];
+            const double rp = P.nu_b * row_residual(P, l, axb) / P.Sy[l];
             acc[1] += rp * rp;                           // SL_RP2
-            acc[2] += P.b[l] * yb;                       // SL_BY
+            acc[2] += row_dual_term(P, l, yb);           // SL_BY
           } else {
             V.y[l] = wy;
             V.Ax[l] = aw;
@@ -1197,7 +1247,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
                                 : spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
-          const double wy = yl + sigma * (P.b[l] - (2.0 * aw - axl));
+          const double wy = dual_candidate(P, l, yl, 2.0 * aw - axl, sigma);
           V.wy[l] = wy;
           V.Aw[l] = aw;
           if (tracing) TB.wy[L.C.ktot * m + l] = wy;
@@ -1205,9 +1255,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             const double dy = yl - wy;
             acc[0] += dy * dy;                           // SL_DY2
             acc[1] += (axl - aw) * dy;                   // SL_ADXDY
-            const double rp = P.nu_b * (aw - P.b[l]) / P.Sy[l];
+            const double rp = P.nu_b * row_residual(P, l, aw) / P.Sy[l];
             acc[2] += rp * rp;                           // SL_RP2
-            acc[3] += P.b[l] * wy;                       // SL_BY
+            acc[3] += row_dual_term(P, l, wy);           // SL_BY
             const double my = wy - V.ay[l];
             acc[4] += my * my;                           // SL_MOVY2
           } else {
@@ -1287,8 +1337,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     dual_check(avg ? V.x : W, avg ? V.y : V.wy, avg ? L.C.hx : L.hu);
     SYNC_OR_EXIT();
     {
-      const int sl[2] = {SL_XQX, SL_RD2};
-      team_reduce(L, part, G, sl, 2);
+      const int sl[3] = {SL_XQX, SL_RD2, SL_BOXD};
+      team_reduce(L, part, G, sl, 3);
     }
     if (avg) {
       if (tid == 0) {

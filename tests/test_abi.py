@@ -129,3 +129,33 @@ def test_batch_binding_needs_two_problems(lib):
 def test_defaults_of_execution_settings(lib):
     s = G.default_settings()
     assert s.autotune == 1 and s.tune_iters == 64 and s.time_kernels == 0
+
+
+def test_setup_rejects_invalid_bounds():
+    """Host validation of the implementation form: NaN or crossed row
+    bounds, a lower endpoint of +inf, and a box block without bounds are
+    PDHCG_E_ARG before any device work."""
+    import math
+    from instances import synth
+    base = synth.bounded_qp(0)
+
+    def setup_rc(p):
+        m = G._Marshalled(p)
+        h = C.c_void_p()
+        return G.load().pdhcg_setup(C.byref(m.pc), 1, C.byref(G.default_settings()), C.byref(h))
+
+    for field, idx, val in (("row_lo", 3, math.nan), ("row_lo", 1, 1e9), ("row_lo", 4, math.inf),
+                            ("x_lo", 0, 5.0), ("x_hi", 1, -math.inf)):
+        p = synth.bounded_qp(0)
+        arr = getattr(p, field).copy()
+        arr[idx] = val
+        setattr(p, field, arr)
+        if field == "row_lo" and val == 1e9:
+            p.row_hi[idx] = 0.0
+        assert setup_rc(p) == -1, (field, idx, val)
+    p = synth.bounded_qp(0)
+    p.x_lo = p.x_hi = None
+    assert setup_rc(p) == -1
+    p = synth.bounded_qp(0)
+    p.row_hi = None
+    assert setup_rc(p) == -1
