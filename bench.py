@@ -17,7 +17,7 @@ Variants (default line): FP32 bulk on the same instance and budget, the
 mixed-cone SOCP/QCQP solve to 1e-6 in FP64 and FP32 bulk, and the batch of
 4096 portfolio QPs against a per-instance loop.  --workload selects another
 workload as the main line (mixed_cone, fisher, tiny_qp, portfolio_batch,
-fisher_warm, mlp_train).
+fisher_warm, mlp_train, fisher_paper --buyers N).
 
 cpu_baseline: the oracle as it stands, one thread, on the first outer
 iterations of the same instance, run in a child process started before the
@@ -417,7 +417,7 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
-def timed_solves(prob, args, budget, precision="fp64"):
+def timed_solves(prob, args, budget, precision="fp64", verbose=0):
     """Setup, warm-up and the timed solves of one instance on torch's current
     stream; returns (runs, wall seconds of the timed solves, setup seconds)."""
     import torch
@@ -425,10 +425,13 @@ def timed_solves(prob, args, budget, precision="fp64"):
     stream = torch.cuda.current_stream()
     extra = {"max_iter": budget} if budget > 0 else {}
     t0 = time.perf_counter()
-    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream, precision=precision, **extra)
+    h = pkg.setup(prob, tol=args.tol, time_kernels=1, stream=stream.cuda_stream, precision=precision,
+                  verbose=verbose, **extra)
     setup_s = time.perf_counter() - t0
+    log(f"setup done ({setup_s:.1f} s, {precision})")
     for _ in range(args.warmup):
-        h.solve()
+        w = h.solve()
+        log(f"warm-up solve: {w['status']} {w['iterations']} it in {w['solve_s']:.2f} s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = [h.solve() for _ in range(args.steps)]
@@ -469,6 +472,42 @@ def mixed_cone_variant(args):
     return out
 
 
+# the paper's single-GPU Fisher times (one H100 80 GB, precision not stated),
+# seconds to relative KKT 1e-4 and 1e-6, by buyer count
+FISHER_PAPER_H100_S = {1_000: (0.36, 0.85), 10_000: (0.69, 0.77), 100_000: (4.43, 4.77),
+                       1_000_000: (46.65, 48.32), 10_000_000: (231.94, 241.53)}
+
+
+def bench_fisher_paper(args):
+    """Paper-shaped Fisher market (buyers --buyers; goods and density of the
+    paper's instance table, U[0.1, 1.1] valuations and budgets, supplies
+    0.2 n): FP64 solves to 1e-4 and to 1e-6 from a cold start, each timed
+    over --steps runs after --warmup, next to the paper's own times."""
+    import torch
+    import paper_2608_09159_amd as pkg
+    from instances import synth
+    t0 = time.perf_counter()
+    prob = synth.fisher_paper(args.buyers)
+    log(f"fisher_paper n={args.buyers}: generated ({time.perf_counter() - t0:.1f} s), "
+        f"N={prob.n} M={prob.m} nnz={prob.A.nnz}")
+    out = {"workload": f"Fisher market, paper shape, {args.buyers} buyers x {prob.meta['n_goods']} goods",
+           "N": prob.n, "M": prob.m, "edges": int(prob.meta["edges"]), "nnz_A": int(prob.A.nnz)}
+    for tol in (1e-4, 1e-6):
+        a2 = argparse.Namespace(**{**vars(args), "tol": tol})
+        runs, wall, setup_s = timed_solves(prob, a2, 0, verbose=1 if prob.n > 1_000_000 else 0)
+        r = runs[-1]
+        out[f"tol_{tol:g}"] = {"time_to_tol_s": wall / args.steps, "iterations": r["iterations"],
+                               "status": r["status"], "rel_kkt": rel_kkt(r), "setup_s": setup_s,
+                               "kernel_s": r["kernel_s"],
+                               "iters_per_s": sum(x["iterations"] for x in runs) / wall}
+        log(f"tol {tol:g}: {r['status']} {r['iterations']} it, {wall / args.steps:.3f} s")
+    paper = FISHER_PAPER_H100_S.get(args.buyers)
+    if paper:
+        out["paper_h100_s"] = {"tol_1e-04": paper[0], "tol_1e-06": paper[1],
+                               "hardware": "one H100 80 GB, precision not stated"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,6 +531,7 @@ def main():
     ap.add_argument("--timed", type=int, default=16, help="fisher_warm: held-out seeds timed one by one")
     ap.add_argument("--epochs", type=int, default=100, help="fisher_warm: training epochs")
     ap.add_argument("--lr", type=float, default=1e-4, help="fisher_warm: Adam learning rate")
+    ap.add_argument("--buyers", type=int, default=100_000, help="fisher_paper: buyer count")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -520,6 +560,9 @@ def main():
         return
     if args.workload == "mlp_train":
         bench_mlp(args)
+        return
+    if args.workload == "fisher_paper":
+        print(json.dumps(bench_fisher_paper(args)), flush=True)
         return
     prob, wname = workload(args.workload)
     if args.workload == "portfolio_batch":

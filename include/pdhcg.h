@@ -76,6 +76,11 @@ extern "C" {
 #define PDHCG_CONE_BOX    6   /* x_i in [x_lo_i, x_hi_i] on each coordinate of
                                  the block (the box set of eq. solver-input;
                                  bounds from pdhcg_problem.x_lo / x_hi)      */
+#define PDHCG_CONE_EXP1   7   /* (z, s, t) with s fixed at 1 and e^z <= t, dim
+                                 3: an exponential-cone block whose middle
+                                 coordinate is fixed at one, as in the Fisher
+                                 experiment (Section "Large-Scale Fisher
+                                 Equilibrium"); a convex set, not a cone    */
 
 /* ---- enumerations in settings ---------------------------------------- */
 #define PDHCG_SCHEME_RH   0   /* reflected-Halpern epochs (eq. rh-update)     */
@@ -166,7 +171,9 @@ typedef struct {
     int32_t lanes_a;              /* lanes per row of A (0 = auto)            */
     int32_t host_poll;            /* outer iterations per launch (default 512)*/
     void*   stream;               /* hipStream_t                              */
-    int32_t verbose;
+    int32_t verbose;              /* bit 0: a progress line on stderr per
+                                     launch (at most every 5 s) in
+                                     pdhcg_solve                             */
     int32_t time_kernels;         /* 1: time every solver launch with HIP
                                      events on `stream` (result.kernel_s)     */
     int32_t autotune;             /* batches: 1 = choose the lanes-per-row
@@ -281,7 +288,8 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count);
  * EXP and the bisection of Prop. power-cone-bisection for POW, all in the
  * diagonal metric of eq. metric-block-projection,
  *     Pi^M_K(r) = argmin_{u in K} 1/2 ||u - r||_M^2,  M = diag(metric).
- * type: PDHCG_CONE_*; dim: coordinates per block (RSOC >= 2, EXP/POW 3).
+ * type: PDHCG_CONE_* except BOX; dim: coordinates per block (RSOC >= 2,
+ * EXP/POW/EXP1 3).
  * r, out: count*dim doubles, block after block, in the coordinate order of
  * the cone list (host pointers, caller-owned).  metric: count*dim positive
  * entries, or NULL for the Euclidean projection; a block whose metric is

@@ -12,7 +12,9 @@ The implementation form of the same section (eq. solver-input) is covered
 by the optional fields: row bounds row_lo <= A x <= row_hi (when given they
 replace A x = b; infinite entries are absent bounds, equal entries
 equalities) and box blocks x_i in [x_lo_i, x_hi_i] (blocks of kind "box";
-x_lo / x_hi have length n and are read at the box coordinates only).
+x_lo / x_hi have length n and are read at the box coordinates only).  Blocks
+of kind "exp1" are exponential-cone blocks (z, s, t) with the middle
+coordinate fixed at one, {(z, 1, t): e^z <= t}, as in the Fisher experiment.
 
 The container holds data only; it performs no solver arithmetic.
 """
@@ -24,7 +26,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 import scipy.sparse as sp
 
-CONE_TYPES = ("free", "nonneg", "soc", "rsoc", "exp", "pow", "box")
+CONE_TYPES = ("free", "nonneg", "soc", "rsoc", "exp", "pow", "box", "exp1")
 
 
 @dataclass

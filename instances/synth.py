@@ -259,19 +259,56 @@ def portfolio_batch(count=4096, base_seed=1_000_000, **kw):
 # ----------------------------------------------------------------------------
 def fisher_graph(n_buyers=1000, n_goods=500, density=0.1, seed=0):
     """Valuation graph: each (buyer, good) pair is an edge with probability
-    ``density``; every buyer and every good gets at least one edge."""
+    ``density``; every buyer and every good gets at least one edge.  Above
+    1e8 pairs the edges are drawn in O(edges) memory: the gaps between
+    successive edges in row-major pair order are geometric(density), which
+    gives the same distribution as independent draws per pair."""
     rng = np.random.default_rng(seed)
-    mask = rng.random((n_buyers, n_goods)) < density
-    for i in np.where(~mask.any(axis=1))[0]:
-        mask[i, rng.integers(n_goods)] = True
-    for j in np.where(~mask.any(axis=0))[0]:
-        mask[rng.integers(n_buyers), j] = True
-    bi, gj = np.nonzero(mask)
+    if n_buyers * n_goods <= 100_000_000:
+        mask = rng.random((n_buyers, n_goods)) < density
+        for i in np.where(~mask.any(axis=1))[0]:
+            mask[i, rng.integers(n_goods)] = True
+        for j in np.where(~mask.any(axis=0))[0]:
+            mask[rng.integers(n_buyers), j] = True
+        bi, gj = np.nonzero(mask)
+        return bi.astype(np.int64), gj.astype(np.int64)
+    total = n_buyers * n_goods
+    chunks, pos = [], -1
+    while pos < total:
+        gaps = rng.geometric(density, size=max(1_000_000, int(1.05 * density * (total - pos))))
+        cand = pos + np.cumsum(gaps)
+        pos = int(cand[-1])
+        chunks.append(cand[cand < total])
+    cells = np.concatenate(chunks)
+    bi, gj = cells // n_goods, cells % n_goods
+    extra = []
+    miss_b = np.setdiff1d(np.arange(n_buyers), bi)
+    extra += [ib * n_goods + rng.integers(n_goods) for ib in miss_b]
+    miss_g = np.setdiff1d(np.arange(n_goods), gj)
+    extra += [rng.integers(n_buyers) * n_goods + jg for jg in miss_g]
+    if extra:
+        cells = np.unique(np.concatenate([cells, np.asarray(extra, dtype=np.int64)]))
+        bi, gj = cells // n_goods, cells % n_goods
     return bi.astype(np.int64), gj.astype(np.int64)
 
 
+# the paper's Fisher instance shapes: buyers -> (goods, density)
+FISHER_PAPER_SHAPES = {1_000: (400, 0.20), 10_000: (4_000, 0.02), 100_000: (4_000, 0.02),
+                       1_000_000: (4_000, 0.02), 10_000_000: (4_000, 0.01)}
+
+
+def fisher_paper(n_buyers=1_000, seed=1, middle="fixed"):
+    """A Fisher market of the paper's experiment: goods and valuation
+    density by the buyer count (FISHER_PAPER_SHAPES), valuations and
+    budgets U[0.1, 1.1], supplies 0.2 n, seed 1 (graph and values drawn with
+    numpy's generator, so the instance matches the paper's in shape only)."""
+    goods, rho = FISHER_PAPER_SHAPES[n_buyers]
+    return fisher(seed=seed, n_buyers=n_buyers, n_goods=goods, density=rho, graph_seed=seed,
+                  dist="paper", middle=middle)
+
+
 def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
-           dist="lognormal", graph=None):
+           dist="lognormal", graph=None, middle="row"):
     """Fisher market in the exponential-cone form of eq. fisher-conic with the
     middle exponential-cone coordinate held at one by an explicit row.
 
@@ -282,7 +319,12 @@ def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
 
     dist="lognormal": u_ij ~ lognormal(0,1), w_i ~ lognormal(0,0.5), b_j = 1.
     dist="paper":     u_ij, w_i ~ U[0.1, 1.1], b_j = 0.2 n (the paper's
-                      Fisher experiment recipe)."""
+                      Fisher experiment recipe).
+    middle="row":     (z_i, s_i, t_i) in an exponential-cone block and a row
+                      s_i = 1 (m + 2n rows);
+    middle="fixed":   the block (z_i, 1, t_i) with its middle coordinate fixed
+                      at one by the set itself (kind "exp1"), as the paper
+                      stores it (m + n rows)."""
     if graph is None:
         graph = fisher_graph(n_buyers, n_goods, density, graph_seed)
     bi, gj = graph
@@ -299,27 +341,32 @@ def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
     else:
         raise ValueError(dist)
     nb = n_buyers
+    fixed = middle == "fixed"
     n = e + 4 * nb
-    m = n_goods + 2 * nb
+    m = n_goods + (1 if fixed else 2) * nb
     off_d = e
     off_c = e + nb
     zi = off_c + 3 * np.arange(nb)
     rows = [gj,                                    # supply rows
             n_goods + bi,                          # t-definition rows (-u x)
             n_goods + np.arange(nb),               # (-delta)
-            n_goods + np.arange(nb),               # (+t)
-            n_goods + nb + np.arange(nb)]          # s_i = 1
-    cols = [np.arange(e), np.arange(e), off_d + np.arange(nb), zi + 2, zi + 1]
-    vals = [np.ones(e), -u, -np.ones(nb), np.ones(nb), np.ones(nb)]
+            n_goods + np.arange(nb)]               # (+t)
+    cols = [np.arange(e), np.arange(e), off_d + np.arange(nb), zi + 2]
+    vals = [np.ones(e), -u, -np.ones(nb), np.ones(nb)]
+    if not fixed:
+        rows.append(n_goods + nb + np.arange(nb))  # s_i = 1
+        cols.append(zi + 1)
+        vals.append(np.ones(nb))
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(m, n))
-    b = np.concatenate([supply, np.zeros(nb), np.ones(nb)])
+    b = np.concatenate([supply, np.zeros(nb)] + ([] if fixed else [np.ones(nb)]))
     c = np.zeros(n)
     c[off_d:off_d + nb] = 1.0
     c[zi] = -w
-    cones = [("nonneg", 0, e + nb, 0.0)] + [("exp", int(z), 3, 0.0) for z in zi]
+    kind = "exp1" if fixed else "exp"
+    cones = [("nonneg", 0, e + nb, 0.0)] + [(kind, int(z), 3, 0.0) for z in zi]
     return Problem(n=n, m=m, A=A, b=b, c=c, cones=cones,
-                   name=f"fisher[{n_buyers}x{n_goods},seed={seed}]",
+                   name=f"fisher[{n_buyers}x{n_goods},seed={seed}{',fixed' if fixed else ''}]",
                    meta={"u": u, "w": w, "graph": graph, "n_buyers": nb,
                          "n_goods": n_goods, "edges": e})
 

@@ -626,6 +626,56 @@ def exp_closest_direct(r0, s0, t0, mr=1.0, ms=1.0, mt=1.0):
 
 
 # ----------------------------------------------------------------------------
+# EXP block with the middle coordinate fixed at one
+# ----------------------------------------------------------------------------
+def exp1_metric_one(r, m=(1.0, 1.0, 1.0)):
+    """Pi^M onto X = {(z, s, t): s = 1, e^z <= t}, the exponential-cone block
+    whose middle coordinate is fixed at one (Section "Large-Scale Fisher
+    Equilibrium"): s = 1, and (z, t) is r's (z, t) when e^z0 <= t0, else the
+    point (z, e^z) where m_z (z - z0) + m_t (e^z - t0) e^z = 0 (stationarity
+    of m_z (z - z0)^2 + m_t (t - t0)^2 on t = e^z, with the multiplier
+    m_t (t - t0) >= 0).  That function is increasing where e^z >= t0 and
+    positive at z0; its root is bisected between z0 and a point where it is
+    negative (log t0 when t0 > 0, else found by stepping down)."""
+    z0, _, t0 = (float(a) for a in r)
+    mz, _, mt = (float(a) for a in m)
+    if z0 <= 709.0 and math.exp(z0) <= t0:
+        return np.array([z0, 1.0, t0])
+
+    def f(z):
+        ez = math.exp(z)
+        return mz * (z - z0) + mt * (ez - t0) * ez
+
+    hi = min(z0, 709.0)
+    if t0 > 0:
+        lo = min(math.log(t0), hi)
+    else:
+        step = 1.0
+        lo = hi - step
+        while f(lo) >= 0:
+            step *= 2.0
+            lo = hi - step
+    z = _bisect_scalar(f, lo, hi, increasing=True)
+    return np.array([z, 1.0, math.exp(z)])
+
+
+def exp1_dual_terms(a, b, c):
+    """For the reduced cost (a, b, c) of an exp1 block: its projection
+    (min(a, 0), b, max(c, 0)) onto Lambda = {a <= 0, c >= 0} (the dual of
+    the set's recession cone {dz <= 0, ds = 0, dt >= 0}) and the infimum
+    over the set of <lambda, x> = b + lambda_a (log(-lambda_a/lambda_c) - 1)
+    (b when lambda_a = 0; -inf when lambda_a < 0 = lambda_c)."""
+    la, lc = min(a, 0.0), max(c, 0.0)
+    if la == 0.0:
+        term = b
+    elif lc == 0.0:
+        term = -math.inf
+    else:
+        term = b + la * (math.log(-la / lc) - 1.0)
+    return (la, b, lc), term
+
+
+# ----------------------------------------------------------------------------
 # POW
 # ----------------------------------------------------------------------------
 def _qroot(s, c):
@@ -700,10 +750,13 @@ class Projector:
     eq. solver-input) clamp, in any diagonal metric; lo and hi have length n
     and are read at the box coordinates."""
 
-    def __init__(self, cones, n, lo=None, hi=None):
+    def __init__(self, cones, n, lo=None, hi=None, kappa=None):
         self.cones = list(cones)
         self.n = n
         self.groups = {}
+        # exp1 blocks in scaled coordinates: the set kappa X with kappa the
+        # block's (common) scale factor; 1 in the original coordinates
+        self.kappa = None if kappa is None else np.asarray(kappa, dtype=float)
         box = [np.arange(st, st + d) for kind, st, d, al in self.cones if kind == "box"]
         self.box_idx = np.concatenate(box) if box else np.zeros(0, dtype=np.int64)
         if self.box_idx.size:
@@ -753,11 +806,14 @@ class Projector:
                 Mb = m[idx[~eu]]
                 out[idx[~eu]] = soc_metric(Rb, Mb) if kind == "soc" else rsoc_metric(Rb, Mb)
         for bi, (kind, st, d, al) in enumerate(self.cones):
-            if kind not in ("exp", "pow"):
+            if kind not in ("exp", "pow", "exp1"):
                 continue
             mm = (1.0, 1.0, 1.0) if (euclid[bi] or m is None) else m[st:st + 3]
             if kind == "exp":
                 out[st:st + 3] = exp_metric_one(r[st:st + 3], mm)
+            elif kind == "exp1":
+                k = 1.0 if self.kappa is None else float(self.kappa[st])
+                out[st:st + 3] = k * exp1_metric_one(r[st:st + 3] / k, mm)
             else:
                 out[st:st + 3] = pow_metric_one(r[st:st + 3], al, mm)
         return out

@@ -30,6 +30,10 @@ Passages followed
   candidate is w_y = sigma (Pi_B(q) - q) with q = A(2 w_x - x) - y/sigma,
   which is y + sigma (b - A(2 w_x - x)) when l = u = b (equality rows use
   that form); boxes clamp in the prox.
+* Exponential blocks with the middle coordinate fixed at one ("exp1", the
+  Fisher experiment's representation): projection onto {(z, 1, t): e^z <= t}
+  scaled to the block's coordinates; KKT terms from the set's recession
+  cone and support function (exp1_dual_terms).
 
 Readings where the paper is silent (each also listed in the design doc):
 * ||A||_2 by 128 power iterations on A^T A from 1/sqrt(n) (overridable);
@@ -72,7 +76,7 @@ from typing import Optional
 import numpy as np
 import scipy.sparse as sp
 
-from .cones import Projector
+from .cones import Projector, exp1_dual_terms
 from .scaling import scale_problem
 
 
@@ -204,11 +208,17 @@ def kkt_residuals(prob, x, y, proj=None):
         lam = box_dual_part(sb, proj.box_lo, proj.box_hi)
         dres[proj.box_idx] = sb - lam
         boxterm = _signed_bound_dot(lam, proj.box_lo, proj.box_hi)
+    for kind, st, d, al in prob.cones:
+        if kind == "exp1":           # fixed-middle exponential blocks
+            lam, term = exp1_dual_terms(*s[st:st + 3])
+            dres[st:st + 3] = s[st:st + 3] - np.array(lam)
+            boxterm += term
     rd = float(np.linalg.norm(dres)) / (1.0 + float(np.linalg.norm(prob.c)))
     xqx = float(x @ Qx)
     pobj = 0.5 * xqx + float(prob.c @ x)
     dobj = by + boxterm - 0.5 * xqx
-    gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
+    # an exp1 reduced cost with lambda_a < 0 = lambda_c has dual value -inf
+    gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj)) if math.isfinite(dobj) else 1.0
     return dict(rel_primal=rp, rel_dual=rd, rel_gap=gap, primal_obj=pobj, dual_obj=dobj)
 
 
@@ -232,7 +242,7 @@ def setup(prob, st: Settings = None):
                        pock_chambolle=st.pock_chambolle,
                        bound_objective=st.bound_objective, enabled=st.scaling)
     q = QOp(sc.P, sc.R, sc.D, prob.n)
-    proj = Projector(prob.cones, prob.n, sc.xlo, sc.xhi)
+    proj = Projector(prob.cones, prob.n, sc.xlo, sc.xhi, kappa=sc.Sx / sc.nu_b)
     euclid_blocks = proj.const_blocks(q.diag)
     a_norm = st.a_norm if st.a_norm > 0 else power_norm(sc.A, st.power_iters)
     if not a_norm > 0:       # A = 0 or no rows: any step size keeps tau sigma ||A||^2 < 1

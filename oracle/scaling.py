@@ -81,6 +81,8 @@ class Scaled:
 
 def _cone_blocks(cones):
     return [(st, d) for kind, st, d, al in cones if kind not in ("free", "nonneg", "box")]
+# (exp1 blocks are cone blocks here: one common factor keeps the set's
+# shape, so the scaled block is kappa X with kappa = S_x / nu_b)
 
 
 def combined_bounds(lo, hi):

@@ -37,7 +37,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdhcg.so")
 
-CONE_CODES = {"free": 0, "nonneg": 1, "soc": 2, "rsoc": 3, "exp": 4, "pow": 5, "box": 6}
+CONE_CODES = {"free": 0, "nonneg": 1, "soc": 2, "rsoc": 3, "exp": 4, "pow": 5, "box": 6, "exp1": 7}
 STATUS = {1: "OPTIMAL", 2: "MAX_ITER", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "ABORTED"}
 SCHEMES = {"rh": 0, "avg": 1}
 INNER = {"jacobi": 0, "euclid": 1}

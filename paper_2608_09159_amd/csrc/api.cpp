@@ -19,6 +19,15 @@ using namespace pdhcg;
 
 namespace {
 
+// row bounds, box blocks or fixed-middle EXP blocks: the kernel variant
+// compiled with that code runs the instance
+bool needs_ext(const HostInstance& H) {
+  if (!H.rlo.empty() || !H.xlo.empty()) return true;
+  for (const ConeBlock& k : H.cones)
+    if (k.type == PDHCG_CONE_EXP1) return true;
+  return false;
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -102,6 +111,7 @@ struct Batch {
   std::vector<long> offx, offy;   // count + 1 prefix sums of n and m
   int grid = 1;
   bool cones = false;             // some instance has SOC/RSOC/EXP/POW blocks
+  bool ext = false;               // some instance has row bounds, boxes or EXP1 blocks
   int div_a = 2, div_at = 2;      // lanes-per-row rule: lanes <= mean nnz / div
   double tune_s = 0.0;
   hipStream_t cap = nullptr;      // private stream used for graph capture
@@ -238,6 +248,7 @@ int upload_instance(Handle* h, Instance* I) {
   P.rhi = H.rhi.empty() ? nullptr : B.upload(H.rhi);
   P.xlo = H.xlo.empty() ? nullptr : B.upload(H.xlo);
   P.xhi = H.xhi.empty() ? nullptr : B.upload(H.xhi);
+  P.ext = needs_ext(H) ? 1 : 0;
   I->qmax = 0.0;
   for (double q : H.qdiag) I->qmax = std::max(I->qmax, q);
 
@@ -764,6 +775,7 @@ void carve_instance(const HostInstance& H, int trace_cap, bool avg, Carve& c, In
   P.rhi = H.rhi.empty() ? nullptr : c.put(H.rhi);
   P.xlo = H.xlo.empty() ? nullptr : c.put(H.xlo);
   P.xhi = H.xhi.empty() ? nullptr : c.put(H.xhi);
+  P.ext = needs_ext(H) ? 1 : 0;
   DevVec& V = D.V;
   V = DevVec{};
   V.x = c.take<double>(n);
@@ -936,8 +948,9 @@ int setup_batch(Handle* h) {
   for (int i = 0; i < count; ++i) {
     const HostInstance& H = h->inst[i]->H;
     if (!H.wave_start.empty() || !H.lane_start.empty()) B->cones = true;
+    if (needs_ext(H)) B->ext = true;
   }
-  const int lim = batch_grid_limit(B->cones);
+  const int lim = batch_grid_limit(B->cones, B->ext);
   B->grid = h->s.grid_dim > 0 ? std::min(h->s.grid_dim, lim) : lim;
   B->grid = std::max(1, std::min(B->grid, count));
 
@@ -984,7 +997,7 @@ int setup_batch(Handle* h) {
           if (rc != PDHCG_OK) return rc;
           HIPCHK(launch_batch_reset(B->d_desc, count, B->d_queue, st));
           HIPCHK(hipEventRecord(e0, st));
-          HIPCHK(launch_batch(batch_args(h, it), B->cones, B->grid, st));
+          HIPCHK(launch_batch(batch_args(h, it), B->cones, B->ext, B->grid, st));
           HIPCHK(hipEventRecord(e1, st));
           HIPCHK(hipEventSynchronize(e1));
           float ms = 0.0f;
@@ -1019,7 +1032,7 @@ int capture_batch(Handle* h) {
   if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = launch_batch_reset(B->d_desc, B->count, B->d_queue, B->cap);
-  if (e == hipSuccess) e = launch_batch(batch_args(h, h->s.max_iter), B->cones, B->grid, B->cap);
+  if (e == hipSuccess) e = launch_batch(batch_args(h, h->s.max_iter), B->cones, B->ext, B->grid, B->cap);
   if (e == hipSuccess)
     e = launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy,
                             h->s.scheme == PDHCG_SCHEME_AVG ? 1 : 0, B->cap);
@@ -1283,6 +1296,17 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
       if (c.ktot >= maxit) { status = PDHCG_MAX_ITER; break; }
       continue;
     }
+    if (h->s.verbose & 1) {
+      // progress of long solves (stderr, at most every 5 s)
+      static thread_local double last_print = 0.0;
+      const double tn = now_s();
+      if (tn - last_print >= 5.0 || c.status != 0) {
+        last_print = tn;
+        std::fprintf(stderr, "pdhcg: %lld it, %lld inner, %lld restarts, rel_p %.2e rel_d %.2e gap %.2e, %.1f s\n",
+                     (long long)c.ktot, (long long)c.inner_total, (long long)c.restarts, c.rel_p, c.rel_d,
+                     c.rel_gap, tn - t0);
+      }
+    }
     if (c.status != 0) { status = c.status; break; }
     if (c.ktot >= maxit) { status = PDHCG_MAX_ITER; break; }
     if (now_s() - t0 > h->s.time_limit) { status = PDHCG_TIME_LIMIT; break; }
@@ -1373,7 +1397,7 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
     BatchArgs pa = batch_args(h, h->s.max_iter);
     pa.ptimes = dpt;
     HIPCHK(launch_batch_reset(B->d_desc, B->count, B->d_queue, st));
-    HIPCHK(launch_batch(pa, B->cones, B->grid, st));
+    HIPCHK(launch_batch(pa, B->cones, B->ext, B->grid, st));
     HIPCHK(launch_batch_gather(B->d_desc, B->count, B->d_offx, B->d_offy, B->d_outx, B->d_outy,
                                h->s.scheme == PDHCG_SCHEME_AVG ? 1 : 0, st));
   } else {
@@ -1437,9 +1461,10 @@ int pdhcg_last_cone_failure(double* rec, int64_t* count) {
 
 int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* alpha, const double* r,
                         const double* metric, double* out) {
-  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;   // no BOX
+  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_EXP1 || type == PDHCG_CONE_BOX || dim < 1 || count < 0)
+    return PDHCG_E_ARG;
   if ((type == PDHCG_CONE_RSOC && dim < 2) ||
-      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) && dim != 3))
+      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW || type == PDHCG_CONE_EXP1) && dim != 3))
     return PDHCG_E_CONE;
   if (count == 0) return PDHCG_OK;
   if (!r || !out || (type == PDHCG_CONE_POW && !alpha)) return PDHCG_E_ARG;

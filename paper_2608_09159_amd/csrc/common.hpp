@@ -54,6 +54,8 @@ struct DevProblem {
   const double* rhi;
   const double* xlo;     // n scaled box bounds (nullable: no box block)
   const double* xhi;
+  int ext;               // row bounds, box or fixed-middle EXP blocks present: the
+                         // kernel variant compiled with them (others leave them out)
   const double* c;       // n (scaled)
   const double* qd;      // n diag(Q^)
   const double* Sx;      // n

@@ -698,6 +698,58 @@ __device__ __forceinline__ void project_pow_body(double x, double y, double z, d
   out[2] = copysign(rho, z);
 }
 
+// ---------------------------------------------------------------------------
+// EXP block with the middle coordinate fixed at one, on one lane: the point
+// (z0, ., t0) projected onto {(z, 1, t): e^z <= t} in the metric (mz, ., mt).
+// Outside the set the projection is (z, 1, e^z) at the root of
+// f(z) = mz (z - z0) + mt (e^z - t0) e^z (stationarity on the boundary with
+// multiplier mt (e^z - t0) >= 0); f increases where e^z >= t0, is positive
+// at z0 and negative at log t0 (t0 > 0) or far enough below z0.  Safeguarded
+// Newton inside the sign bracket.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp1_f(double z, double z0, double t0, double mz, double mt, double& df) {
+  const double ez = exp(z);
+  df = mz + mt * ez * (2.0 * ez - t0);
+  return mz * (z - z0) + mt * (ez - t0) * ez;
+}
+
+__device__ __forceinline__ void project_exp1_body(double z0, double t0, double mz, double mt, double out[3]) {
+  out[1] = 1.0;
+  if (z0 <= 709.0 && exp(z0) <= t0) { out[0] = z0; out[2] = t0; return; }
+  double hi = fmin(z0, 709.0), lo, d;
+  if (t0 > 0.0) {
+    lo = fmin(log(t0), hi);
+  } else {
+    double step = 1.0;
+    lo = hi - step;
+    while (exp1_f(lo, z0, t0, mz, mt, d) >= 0.0 && step < 1e300) {
+      step *= 2.0;
+      lo = hi - step;
+    }
+  }
+  // at the root mz (z0 - z) = mt (e^z - t0) e^z >= mt (e^z - t0+)^2 with
+  // z >= lo, so e^z <= t0+ + sqrt((mz/mt)(z0 - lo)): a tight upper end (from
+  // z0 itself Newton would creep down by about 1/2 per step where the
+  // e^(2z) term dominates)
+  hi = fmin(hi, log(fmax(t0, 0.0) + sqrt((mz / mt) * (z0 - lo))));
+  if (hi < lo) hi = lo;
+  double z = hi;
+  const double tol = 1e-15 * fmax(1.0, fabs(hi));
+  for (int it = 0; it < 2000 && hi - lo > tol; ++it) {
+    const double fz = exp1_f(z, z0, t0, mz, mt, d);
+    if (fz > 0.0) hi = z;
+    else if (fz < 0.0) lo = z;
+    else { lo = hi = z; break; }
+    double zn = (d > 0.0) ? z - fz / d : 0.5 * (lo + hi);
+    if (fabs(zn - z) <= 2.220446049250313e-16 * fmax(1.0, fabs(z))) { lo = hi = zn; break; }   // converged
+    if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+    z = zn;
+  }
+  z = 0.5 * (lo + hi);
+  out[0] = z;
+  out[2] = exp(z);
+}
+
 // Out-of-line entry points (one copy of each root-finder in the code, kept
 // apart from the register allocation of the solver loop); the projected
 // point comes back in registers, not through the caller's stack.
@@ -717,6 +769,14 @@ __device__ __noinline__ Trip project_pow(double x, double y, double z, double al
   double o[3];
   project_pow_body(x, y, z, al, mx, my, mz, o, warm);
   return Trip{o[0], o[1], o[2]};
+}
+
+// the fixed-middle EXP block kappa X in scaled coordinates (kappa the
+// block's common scale): kappa Pi^M_X(r / kappa)
+__device__ __forceinline__ Trip project_exp1(double z0, double t0, double mz, double mt, double kappa) {
+  double o[3];
+  project_exp1_body(z0 / kappa, t0 / kappa, mz, mt, o);
+  return Trip{kappa * o[0], kappa * o[1], kappa * o[2]};
 }
 
 }  // namespace pdhcg

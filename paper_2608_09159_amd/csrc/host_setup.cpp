@@ -244,6 +244,7 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
         if (cb.dim < 2) return PDHCG_E_CONE;
         break;
       case PDHCG_CONE_EXP:
+      case PDHCG_CONE_EXP1:
         if (cb.dim != 3) return PDHCG_E_CONE;
         break;
       case PDHCG_CONE_POW:

@@ -502,15 +502,30 @@ __device__ __forceinline__ double dual_candidate(const DevProblem& P, long l, do
   return yl + sigma * (P.b[l] - axb);
 }
 
+template <bool EXT>
+__device__ __forceinline__ double eproj(const DevProblem& P, long i, uint8_t ct, double z) {
+  if constexpr (EXT) return elem_proj_i(P, i, ct, z);
+  else return elem_proj(ct, z);
+}
+
+template <bool EXT>
+__device__ __forceinline__ double dual_cand(const DevProblem& P, long l, double yl, double axb, double sigma) {
+  if constexpr (EXT) return dual_candidate(P, l, yl, axb, sigma);
+  else return yl + sigma * (P.b[l] - axb);
+}
+
 // (A x)_l minus its nearest point of the row's bounds (scaled)
+template <bool EXT>
 __device__ __forceinline__ double row_residual(const DevProblem& P, long l, double ax) {
-  return P.rlo ? ax - fmin(fmax(ax, P.rlo[l]), P.rhi[l]) : ax - P.b[l];
+  if constexpr (EXT) return P.rlo ? ax - fmin(fmax(ax, P.rlo[l]), P.rhi[l]) : ax - P.b[l];
+  else return ax - P.b[l];
 }
 
 // the row's term of the dual objective: b_l y_l, or with bounds
 // y^+ l - y^- u (the endpoint the sign of y selects)
+template <bool EXT>
 __device__ __forceinline__ double row_dual_term(const DevProblem& P, long l, double y) {
-  if (!P.rlo) return P.b[l] * y;
+  if (!EXT || !P.rlo) return P.b[l] * y;
   return y > 0.0 ? y * P.rlo[l] : (y < 0.0 ? y * P.rhi[l] : 0.0);
 }
 
@@ -637,9 +652,10 @@ __device__ Items cache_items(const DevProblem& P, Items I, Lds& L) {
 // warm (nullable): previous roots of the root-finding projections, one per
 // item (wave items first, then lane items), read as starting points and
 // overwritten with the new roots
-template <class MakeSrc>
+template <bool EXT = false, class MakeSrc>
 __device__ __forceinline__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
-                              double* dst, double* warm, unsigned long long* ptw = nullptr, long dbase = 0) {
+                              double* dst, double* warm, unsigned long long* ptw = nullptr, long dbase = 0,
+                              bool kkt = false) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;                       // groups per wave
   for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
@@ -665,8 +681,22 @@ __device__ __forceinline__ void project_items(const DevProblem& P, const Items& 
       double m0 = 1.0, m1 = 1.0, m2 = 1.0;
       if (!eu) { m0 = src.m(0); m1 = src.m(1); m2 = src.m(2); }
       double* w = warm ? warm + P.n_wave + it : nullptr;
-      const Trip o = li_type(P, I, it) == PDHCG_CONE_EXP ? project_exp(r0, r1, r2, m0, m1, m2, w)
-                                                         : project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, w);
+      const int ty = li_type(P, I, it);
+      Trip o;
+      if constexpr (EXT) {
+        // fixed-middle EXP block: kappa X with kappa = S_x / nu_b of the
+        // block; its KKT terms are not a projection of -s (kkt: zeros here,
+        // the check takes the terms itself)
+        if (ty == PDHCG_CONE_EXP1) {
+          o = kkt ? Trip{0.0, 0.0, 0.0} : project_exp1(r0, r2, m0, m2, P.Sx[st] / P.nu_b);
+          dst[st - dbase] = o.a;
+          dst[st + 1 - dbase] = o.b;
+          dst[st + 2 - dbase] = o.c;
+          continue;
+        }
+      }
+      if (ty == PDHCG_CONE_EXP) o = project_exp(r0, r1, r2, m0, m1, m2, w);
+      else o = project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, w);
       dst[st - dbase] = o.a;
       dst[st + 1 - dbase] = o.b;
       dst[st + 2 - dbase] = o.c;
@@ -714,7 +744,10 @@ struct Own {
   const int* atseg;
 };
 
-template <bool CONES, class MV, class Team>
+// EXT: the variant with row bounds, box blocks and fixed-middle EXP blocks
+// (problems without them run the variant compiled without that code, whose
+// register allocation is that of the plain method)
+template <bool CONES, class MV, bool EXT, class Team>
 __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, Ctl* ctl,
                            const Team& T, Lds& L, const Own& own, bool prof) {
   const Bulk<MV> M(P);
@@ -797,12 +830,12 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if constexpr (SOLO) hw_clear(L);
     for_range(c0, c1, [&](long i, bool act) {
       bool el = act && P.ctype[i] != CT_CONE;
-      double x = el ? elem_proj_i(P, i, P.ctype[i], V.zb[i]) : 0.0;
+      double x = el ? eproj<EXT>(P, i, P.ctype[i], V.zb[i]) : 0.0;
       if (el) { V.x[i] = x; V.ax[i] = x; }
       if constexpr (SOLO) hw_add(L, R64, r, i, x, el);
     });
     if (has_items) {
-      project_items(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
+      project_items<EXT>(P, IT, true, [&](long st) { return BufSrc{V.zb, unitM, st}; }, V.zb, nullptr);
       for_item_coords(P, IT, [&](long i, bool act) {
         double x = act ? V.zb[i] : 0.0;
         if (act) { V.x[i] = x; V.ax[i] = x; }
@@ -857,7 +890,8 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     if (!P.q_diag && P.P_ptr && !P.p_diag) spmv_range(P.P_ptr, P.P_col, P.P_val, X, V.t2, c0, c1, La);
     if (!P.q_diag) make_ht(L, P, hX);
     else __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int NSL = EXT ? 3 : 2;
+    double acc[NSL] = {};
     for_range(c0, c1, [&](long i, bool act) {
       if (!act) return;
       const double wi = X[i];
@@ -874,29 +908,43 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       const uint8_t ct = P.ctype[i];
       if (ct == CT_FREE) acc[1] += so * so;
       else if (ct == CT_NONNEG) { const double t = fmax(-so, 0.0); acc[1] += t * t; }
-      else if (ct == CT_BOX) {
+      else if (EXT && ct == CT_BOX) {
         // distance of s to the reduced cost's set, and lambda^+ l - lambda^- u
         const double lo = P.xlo[i], hi = P.xhi[i];
         const double t = so - box_dual_proj(lo, hi, so);
         acc[1] += t * t;
         const double lam = box_dual_proj(lo, hi, si);
-        acc[2] += lam > 0.0 ? lam * lo : (lam < 0.0 ? lam * hi : 0.0);   // SL_BOXD
+        acc[NSL - 1] += lam > 0.0 ? lam * lo : (lam < 0.0 ? lam * hi : 0.0);   // SL_BOXD
       }
       else V.s[i] = si;
     });
     if (has_items) {
       __syncthreads();
-      project_items(P, IT, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb,
-                    V.warm + (P.n_wave + P.n_lane));
+      project_items<EXT>(P, IT, true, [&](long st) { return NegSrc{V.s, st}; }, V.zb,
+                    V.warm + (P.n_wave + P.n_lane), nullptr, 0, true);
       for_item_coords(P, IT, [&](long i, bool act) {
         if (act) {
           const double f = P.nu_c * P.Sx[i] * V.zb[i];
           acc[1] += f * f;
         }
       });
+      // fixed-middle EXP blocks, with the reduced cost (a, b, c) unscaled:
+      // distance to Lambda = {a <= 0, c >= 0} (the dual of the set's
+      // recession cone {dz <= 0, ds = 0, dt >= 0}) and the set's support
+      // term inf <lambda, x> = b + lambda_a (log(-lambda_a/lambda_c) - 1)
+      for (int it = IT.l0 + tid; EXT && it < IT.l1; it += BLOCK) {
+        if (li_type(P, IT, it) != PDHCG_CONE_EXP1) continue;
+        const long st = li_start(P, IT, it);
+        const double f = P.nu_c * P.Sx[st];
+        const double a = f * V.s[st], b = f * V.s[st + 1], c = f * V.s[st + 2];
+        const double la = fmin(a, 0.0), lc = fmax(c, 0.0);
+        acc[1] += (a - la) * (a - la) + (c - lc) * (c - lc);
+        const double term = la == 0.0 ? b : (lc == 0.0 ? -INFINITY : b + la * (log(-la / lc) - 1.0));
+        acc[NSL - 1] += term / (P.nu_b * P.nu_c);
+      }
     }
     const int sl[3] = {SL_XQX, SL_RD2, SL_BOXD};
-    block_store(L, acc, sl, 3, part, G, rank);
+    block_store(L, acc, sl, NSL, part, G, rank);
   };
 
   // residuals, objectives and status from the reduced slots SL_RP2, SL_RD2,
@@ -907,8 +955,15 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     C.rel_p = sqrt(sc[SL_RP2]) / (1.0 + P.norm_b);
     C.rel_d = sqrt(sc[SL_RD2]) / (1.0 + P.norm_c);
     C.pobj = scale * (0.5 * sc[SL_XQX] + sc[SL_CX]);
-    C.dobj = scale * (sc[SL_BY] + sc[SL_BOXD] - 0.5 * sc[SL_XQX]);
-    C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
+    if constexpr (EXT) {
+      C.dobj = scale * (sc[SL_BY] + sc[SL_BOXD] - 0.5 * sc[SL_XQX]);
+      // a fixed-middle EXP reduced cost with lambda_a < 0 = lambda_c has
+      // dual value -inf: no gap closure yet
+      C.rel_gap = C.dobj == -INFINITY ? 1.0 : fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
+    } else {
+      C.dobj = scale * (sc[SL_BY] - 0.5 * sc[SL_XQX]);
+      C.rel_gap = fabs(C.pobj - C.dobj) / (1.0 + fabs(C.pobj) + fabs(C.dobj));
+    }
     if (bad || !isfinite(C.rel_p) || !isfinite(C.rel_d) || !isfinite(C.rel_gap)) {
       C.status = PDHCG_NUMERICAL;
     } else if (fmax(C.rel_p, fmax(C.rel_d, C.rel_gap)) <= S.tol) {
@@ -954,12 +1009,12 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         const double vi = V.x[i] + tau * V.t1[i];
         const double mi = 1.0 + tau * P.qd[i];
         const double z = (vi - tau * P.c[i]) / mi;
-        if (P.ctype[i] != CT_CONE) V.wx[i] = elem_proj_i(P, i, P.ctype[i], z);
+        if (P.ctype[i] != CT_CONE) V.wx[i] = eproj<EXT>(P, i, P.ctype[i], z);
         else V.zb[i] = z;
       });
       if (has_items) {
         __syncthreads();
-        PROJ(project_items(P, IT, false, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.wx, V.warm));
+        PROJ(project_items<EXT>(P, IT, false, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.wx, V.warm));
       }
     } else {
       // acc: ||s||^2, <s, M s>, <s, P s> of the first step s = u - x (the
@@ -982,7 +1037,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           V.up[i] = xi;
           if (P.ctype[i] != CT_CONE) {
             el = true;
-            un = elem_proj_i(P, i, P.ctype[i], z);
+            un = eproj<EXT>(P, i, P.ctype[i], z);
             V.u[i] = un;
             const double si = un - xi;
             acc[0] += si * si;
@@ -998,7 +1053,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
       });
       if (has_items) {
         __syncthreads();
-        PROJ(project_items(P, IT, !jac, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb, V.warm));
+        PROJ(project_items<EXT>(P, IT, !jac, [&](long st) { return BufSrc{V.zb, Mq, st}; }, V.zb, V.warm));
         for_item_coords(P, IT, [&](long i, bool act) {
           double un = 0.0;
           if (act) {
@@ -1100,7 +1155,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             }
             if (el) {
               const double mi = Mq(i);
-              un = elem_proj_i(P, i, P.ctype[i], ui - alpha * gi / mi);
+              un = eproj<EXT>(P, i, P.ctype[i], ui - alpha * gi / mi);
               const double si = un - ui;
               acc[0] += si * si;
               if (fuse) {
@@ -1117,7 +1172,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         });
         if (has_items) {
           if (fuse) __syncthreads();
-          PROJ(project_items(P, IT, !jac,
+          PROJ(project_items<EXT>(P, IT, !jac,
                              [&](long st) { return StepSrc{V.u, gst, Mq, alpha, st, gsb}; }, zst, V.warm,
                              prof ? &L.pt[PT_WCALL] : nullptr, zsb));
           for_item_coords(P, IT, [&](long i, bool act) {
@@ -1171,7 +1226,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
         const double aw = spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
-          const double wy = dual_candidate(P, l, yl, 2.0 * aw - axl, sigma);
+          const double wy = dual_cand<EXT>(P, l, yl, 2.0 * aw - axl, sigma);
           V.wy[l] = wy;
           V.Aw[l] = aw;
           if (tracing) TB.wy[L.C.ktot * m + l] = wy;
@@ -1182,9 +1237,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
           if (ep_end) {
             V.y[l] = yb;
             V.Ax[l] = axb;
-            const double rp = P.nu_b * row_residual(P, l, axb) / P.Sy[l];
+            const double rp = P.nu_b * row_residual<EXT>(P, l, axb) / P.Sy[l];
             acc[1] += rp * rp;                           // SL_RP2
-            acc[2] += row_dual_term(P, l, yb);           // SL_BY
+            acc[2] += row_dual_term<EXT>(P, l, yb);           // SL_BY
           } else {
             V.y[l] = wy;
             V.Ax[l] = aw;
@@ -1247,7 +1302,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
                                 : spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
         if (act && sub == 0) {
           const double yl = V.y[l], axl = V.Ax[l];
-          const double wy = dual_candidate(P, l, yl, 2.0 * aw - axl, sigma);
+          const double wy = dual_cand<EXT>(P, l, yl, 2.0 * aw - axl, sigma);
           V.wy[l] = wy;
           V.Aw[l] = aw;
           if (tracing) TB.wy[L.C.ktot * m + l] = wy;
@@ -1255,9 +1310,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             const double dy = yl - wy;
             acc[0] += dy * dy;                           // SL_DY2
             acc[1] += (axl - aw) * dy;                   // SL_ADXDY
-            const double rp = P.nu_b * row_residual(P, l, aw) / P.Sy[l];
+            const double rp = P.nu_b * row_residual<EXT>(P, l, aw) / P.Sy[l];
             acc[2] += rp * rp;                           // SL_RP2
-            acc[3] += row_dual_term(P, l, wy);           // SL_BY
+            acc[3] += row_dual_term<EXT>(P, l, wy);           // SL_BY
             const double my = wy - V.ay[l];
             acc[4] += my * my;                           // SL_MOVY2
           } else {
@@ -1338,7 +1393,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     SYNC_OR_EXIT();
     {
       const int sl[3] = {SL_XQX, SL_RD2, SL_BOXD};
-      team_reduce(L, part, G, sl, 3);
+      team_reduce(L, part, G, sl, EXT ? 3 : 2);
     }
     if (avg) {
       if (tid == 0) {
@@ -1451,7 +1506,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
 // ---------------------------------------------------------------------------
 // single-problem kernel: the whole grid is one team
 // ---------------------------------------------------------------------------
-template <class MV, bool SOLO>
+template <class MV, bool SOLO, bool EXT>
 __device__ void solve_body(const KArgs& A) {
   __shared__ Lds L;
   const int rank = blockIdx.x, G = gridDim.x;
@@ -1480,10 +1535,10 @@ __device__ void solve_body(const KArgs& A) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull, A.lds_bytes > 0 ? dyn_lds : nullptr, A.lds_bytes};
   if constexpr (SOLO) {
-    run_solver<true, MV>(run, P, A.V, A.ctl, SoloTeam{}, L, own, prof);
+    run_solver<true, MV, EXT>(run, P, A.V, A.ctl, SoloTeam{}, L, own, prof);
   } else {
     GridTeam T{A.bar, A.spin_limit, rank, G};
-    run_solver<true, MV>(run, P, A.V, A.ctl, T, L, own, prof);
+    run_solver<true, MV, EXT>(run, P, A.V, A.ctl, T, L, own, prof);
   }
   tmark(L, prof, PT_INIT);
   __syncthreads();
@@ -1491,14 +1546,19 @@ __device__ void solve_body(const KArgs& A) {
   if (rank == 0 && threadIdx.x == 0 && L.C.status != PDHCG_ABORTED) *A.ctl = L.C;
 }
 
-__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<double, false>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<double, false, false>(A); }
+
+// row bounds, boxes and fixed-middle EXP blocks
+__global__ __launch_bounds__(BLOCK) void solve_kernel_ext(KArgs A) { solve_body<double, false, true>(A); }
 
 // FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
-__global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false, false>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel_f32_ext(KArgs A) { solve_body<float, false, true>(A); }
 
 // a grid of one workgroup: workgroup barriers and the single-workgroup
 // reductions of the batch kernels (the same arithmetic as a batch solve)
-__global__ __launch_bounds__(BLOCK) void solve_kernel_one(KArgs A) { solve_body<double, true>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel_one(KArgs A) { solve_body<double, true, false>(A); }
+__global__ __launch_bounds__(BLOCK) void solve_kernel_one_ext(KArgs A) { solve_body<double, true, true>(A); }
 
 // ---------------------------------------------------------------------------
 // setup kernels: CSR SpMV and deterministic two-pass norms (power iteration)
@@ -1595,7 +1655,7 @@ __global__ __launch_bounds__(BLOCK) void batch_reset_kernel(const InstDesc* desc
 // persistent batch solve: each workgroup takes the next queue position,
 // solves that instance to termination with the single-workgroup team, and
 // stores its control block; instances are queued largest first
-template <bool CONES>
+template <bool CONES, bool EXT>
 __device__ void batch_body(const BatchArgs& B) {
   __shared__ Lds L;
   __shared__ int slot;
@@ -1628,7 +1688,7 @@ __device__ void batch_body(const BatchArgs& B) {
       own.atperm = nullptr;
       own.atseg = nullptr;
       const Run run{&B.S, &D.T, B.stop_at, D.qmax, deadline, nullptr, 0};
-      run_solver<CONES, double>(run, D.P, D.V, D.ctl, SoloTeam{}, L, own, prof);
+      run_solver<CONES, double, EXT>(run, D.P, D.V, D.ctl, SoloTeam{}, L, own, prof);
       tmark(L, prof, PT_INIT);
       __syncthreads();
       if (threadIdx.x == 0) *D.ctl = L.C;
@@ -1638,10 +1698,12 @@ __device__ void batch_body(const BatchArgs& B) {
   if (prof && threadIdx.x < PT_COUNT) B.ptimes[(size_t)blockIdx.x * PT_COUNT + threadIdx.x] = L.pt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs B) { batch_body<true>(B); }
+__global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs B) { batch_body<true, false>(B); }
+__global__ __launch_bounds__(BLOCK) void batch_kernel_ext(BatchArgs B) { batch_body<true, true>(B); }
 
 // batches without cone blocks: 4 waves per SIMD (two instances per CU)
-__global__ __launch_bounds__(BLOCK, 4) void batch_kernel_lin(BatchArgs B) { batch_body<false>(B); }
+__global__ __launch_bounds__(BLOCK, 4) void batch_kernel_lin(BatchArgs B) { batch_body<false, false>(B); }
+__global__ __launch_bounds__(BLOCK, 4) void batch_kernel_lin_ext(BatchArgs B) { batch_body<false, true>(B); }
 
 // ||A^||_2 of every instance: the power iteration of the single-problem
 // setup (128 steps of A^T A from 1/sqrt(n), normalised each step), one
@@ -1734,14 +1796,15 @@ __global__ __launch_bounds__(BLOCK) void project_kernel(int type, int dim, long 
       project_wave_item(type, dim, euclid[b] != 0, ArrSrc{r, m, st},
                         [out, st](int j, double v) { out[st + j] = v; }, nullptr, lg);
     }
-  } else if (type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) {
+  } else if (type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW || type == PDHCG_CONE_EXP1) {
     for (long b = gtid; b < count; b += nthr) {
       const long st = 3 * b;
       const bool eu = euclid[b] != 0;
       const double m0 = eu ? 1.0 : m[st], m1 = eu ? 1.0 : m[st + 1], m2 = eu ? 1.0 : m[st + 2];
       const Trip o = type == PDHCG_CONE_EXP ? project_exp(r[st], r[st + 1], r[st + 2], m0, m1, m2, nullptr)
-                                            : project_pow(r[st], r[st + 1], r[st + 2], alpha[b], m0, m1, m2,
-                                                          nullptr);
+                     : type == PDHCG_CONE_POW ? project_pow(r[st], r[st + 1], r[st + 2], alpha[b], m0, m1, m2,
+                                                            nullptr)
+                                              : project_exp1(r[st], r[st + 2], m0, m2, 1.0);
       out[st] = o.a;
       out[st + 1] = o.b;
       out[st + 2] = o.c;
@@ -1765,8 +1828,10 @@ int block_size() { return BLOCK; }
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream) {
   KArgs a = args;
   void* params[] = {&a};
-  const void* k = fp32 ? (const void*)solve_kernel_f32
-                       : (grid == 1 ? (const void*)solve_kernel_one : (const void*)solve_kernel);
+  const bool ext = args.P.ext != 0;
+  const void* k = fp32 ? (ext ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32)
+                       : (grid == 1 ? (ext ? (const void*)solve_kernel_one_ext : (const void*)solve_kernel_one)
+                                    : (ext ? (const void*)solve_kernel_ext : (const void*)solve_kernel));
   int dev = 0, ncu = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1784,10 +1849,15 @@ hipError_t max_resident_grid(int* out) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)solve_kernel, BLOCK, 0);
   if (e != hipSuccess) return e;
-  int per32 = 0;
+  int per32 = 0, perx = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)solve_kernel_f32, BLOCK, 0);
   if (e != hipSuccess) return e;
-  *out = std::min(per, per32) * ncu;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&perx, (const void*)solve_kernel_ext, BLOCK, 0);
+  if (e != hipSuccess) return e;
+  per = std::min(per, perx);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&perx, (const void*)solve_kernel_f32_ext, BLOCK, 0);
+  if (e != hipSuccess) return e;
+  *out = std::min(per, std::min(per32, perx)) * ncu;
   return hipSuccess;
 }
 
@@ -1883,7 +1953,7 @@ hipError_t launch_project(int type, int dim, long count, const double* alpha, co
     // the group width the solver gives a block of this size
     lg = dim <= 17 ? 16 : (dim <= 33 ? 32 : 64);
     threads = count * lg;
-  } else if (type != PDHCG_CONE_EXP && type != PDHCG_CONE_POW) {
+  } else if (type != PDHCG_CONE_EXP && type != PDHCG_CONE_POW && type != PDHCG_CONE_EXP1) {
     threads = count * (long)dim;
   }
   const long grid = std::max<long>(1, std::min<long>((threads + BLOCK - 1) / BLOCK, 4096));
@@ -1892,19 +1962,24 @@ hipError_t launch_project(int type, int dim, long count, const double* alpha, co
   return hipGetLastError();
 }
 
-int batch_grid_limit(bool cones) {
+static const void* batch_kernel_for(bool cones, bool ext) {
+  return cones ? (ext ? (const void*)batch_kernel_ext : (const void*)batch_kernel)
+               : (ext ? (const void*)batch_kernel_lin_ext : (const void*)batch_kernel_lin);
+}
+
+int batch_grid_limit(bool cones, bool ext) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
-  const void* k = cones ? (const void*)batch_kernel : (const void*)batch_kernel_lin;
+  const void* k = batch_kernel_for(cones, ext);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, BLOCK, 0) != hipSuccess) return ncu;
   return std::max(1, per * ncu);
 }
 
-hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t st) {
-  if (cones) hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(BLOCK), 0, st, args);
-  else hipLaunchKernelGGL(batch_kernel_lin, dim3(grid), dim3(BLOCK), 0, st, args);
-  return hipGetLastError();
+hipError_t launch_batch(const BatchArgs& args, bool cones, bool ext, int grid, hipStream_t st) {
+  BatchArgs a = args;
+  void* params[] = {&a};
+  return hipLaunchKernel(batch_kernel_for(cones, ext), dim3(grid), dim3(BLOCK), params, 0, st);
 }
 
 hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipStream_t st) {
@@ -1914,7 +1989,7 @@ hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipSt
 }
 
 hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double* out, hipStream_t st) {
-  const int grid = std::max(1, std::min(count, batch_grid_limit(false)));
+  const int grid = std::max(1, std::min(count, batch_grid_limit(false, false)));
   hipLaunchKernelGGL(batch_power_kernel, dim3(grid), dim3(BLOCK), 0, st, desc, count, iters, out);
   return hipGetLastError();
 }
@@ -1967,9 +2042,10 @@ extern "C" int pdhcg_project_cones_noalloc(int32_t type, int32_t dim, int64_t co
                                            const double* r, const double* metric, double* out,
                                            void* stream) {
   using namespace pdhcg;
-  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_POW || dim < 1 || count < 0) return PDHCG_E_ARG;
+  if (type < PDHCG_CONE_FREE || type > PDHCG_CONE_EXP1 || type == PDHCG_CONE_BOX || dim < 1 || count < 0)
+    return PDHCG_E_ARG;
   if ((type == PDHCG_CONE_RSOC && dim < 2) ||
-      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW) && dim != 3))
+      ((type == PDHCG_CONE_EXP || type == PDHCG_CONE_POW || type == PDHCG_CONE_EXP1) && dim != 3))
     return PDHCG_E_CONE;
   if (count > kNoAllocMaxBlocks) return PDHCG_E_ARG;
   if (count == 0) return PDHCG_OK;

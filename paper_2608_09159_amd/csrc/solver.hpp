@@ -27,8 +27,8 @@ hipError_t launch_project(int type, int dim, long count, const double* alpha, co
                           const double* m, const unsigned char* euclid, double* out, hipStream_t st);
 
 // batch solve (one workgroup per instance)
-int batch_grid_limit(bool cones);
-hipError_t launch_batch(const BatchArgs& args, bool cones, int grid, hipStream_t st);
+int batch_grid_limit(bool cones, bool ext);
+hipError_t launch_batch(const BatchArgs& args, bool cones, bool ext, int grid, hipStream_t st);
 hipError_t launch_batch_reset(const InstDesc* desc, int count, int* queue, hipStream_t st);
 hipError_t launch_batch_power(const InstDesc* desc, int count, int iters, double* out, hipStream_t st);
 hipError_t launch_batch_gather(const InstDesc* desc, int count, const long* offx, const long* offy,

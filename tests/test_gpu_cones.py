@@ -262,3 +262,29 @@ def test_elementwise_projection():
     R = rng.standard_normal((1000, 4))
     np.testing.assert_array_equal(G.project_cones("free", R), R)
     np.testing.assert_array_equal(G.project_cones("nonneg", R), np.maximum(R, 0.0))
+
+
+@pytest.mark.parametrize("metric", [False, True], ids=["euclid", "metric"])
+def test_exp1_projection_parity(metric):
+    """Exponential block with the middle coordinate fixed at one: points
+    inside, with t0 <= 0, near the boundary, at large and small scales."""
+    rng = np.random.default_rng(501 + metric)
+    n = N_BIG
+    R = rng.standard_normal((n, 3)) * _scales(rng, n, -1, 1)[:, None]
+    parts = np.array_split(rng.permutation(n), 6)
+    R[parts[0], 2] = -np.abs(R[parts[0], 2])
+    R[parts[1], 2] = np.exp(R[parts[1], 0]) * rng.uniform(1, 2, parts[1].size)
+    R[parts[2], 2] = np.exp(R[parts[2], 0]) * (1 + rng.choice([-1, 1], parts[2].size) * 1e-15)
+    R[parts[3], 0] *= 5.0
+    R[parts[4], 2] *= 1e6
+    # far outside: z0 up to ~700 with t0 of either sign (where the e^(2z)
+    # term dominates the stationarity function)
+    p5 = parts[5]
+    R[p5, 0] = rng.uniform(20.0, 700.0, p5.size)
+    R[p5, 2] = rng.standard_normal(p5.size) * 10.0 ** rng.uniform(-1, 3, p5.size)
+    M = _metric(rng, (n, 3)) if metric else None
+    dev = G.project_cones("exp1", R, M)
+    ref = np.empty_like(R)
+    for i in range(n):
+        ref[i] = OC.exp1_metric_one(R[i], (1.0, 1.0, 1.0) if M is None else M[i])
+    _compare(f"exp1 {'metric' if metric else 'euclid'}", dev, ref, R)

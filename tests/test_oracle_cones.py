@@ -435,3 +435,67 @@ def test_projector_groups_match_single_calls():
     np.testing.assert_allclose(out[11:14], C.exp_metric_one(r[11:14], m[11:14]))
     np.testing.assert_allclose(out[14:17], C.pow_metric_one(r[14:17], 0.35, m[14:17]))
     np.testing.assert_array_equal(out[17:], np.maximum(r[17:], 0))
+
+
+# ---------------------------------------------------------------------------
+# exponential block with the middle coordinate fixed at one (Fisher form)
+# ---------------------------------------------------------------------------
+def _exp1_inputs(rng, n=400):
+    R = rng.standard_normal((n, 3)) * 10.0 ** rng.uniform(-1, 1, (n, 1))
+    R[: n // 4, 2] = -np.abs(R[: n // 4, 2])          # t0 <= 0
+    R[n // 4: n // 2, 2] = np.exp(R[n // 4: n // 2, 0]) * rng.uniform(1, 2, n // 4)   # inside
+    return R
+
+
+def test_exp1_projection_kkt():
+    """u = Pi^M_X(r) for X = {(z, 1, t): e^z <= t}: u in X, and M(r - u) is a
+    normal of X at u: zero in (z, t) inside, else (lam e^z, ., -lam) with
+    lam >= 0 (the s entry is free: s is fixed)."""
+    from oracle import cones as OC
+    rng = np.random.default_rng(51)
+    R = _exp1_inputs(rng)
+    M = 10.0 ** rng.uniform(-1, 1, R.shape)
+    for r, m in zip(R, M):
+        u = OC.exp1_metric_one(r, m)
+        assert u[1] == 1.0 and math.exp(u[0]) <= u[2] * (1 + 1e-14)
+        gz, gt = m[0] * (r[0] - u[0]), m[2] * (r[2] - u[2])
+        if math.exp(r[0]) <= r[2]:
+            assert u[0] == r[0] and u[2] == r[2]
+        else:
+            lam = -gt
+            assert lam >= -1e-12 * max(1, abs(gt))
+            assert gz == pytest.approx(lam * math.exp(u[0]), rel=1e-9, abs=1e-12)
+
+
+def test_exp1_projection_brute_force():
+    """Against a dense search over the boundary z (and the point itself when
+    it is inside) in the metric distance."""
+    from oracle import cones as OC
+    rng = np.random.default_rng(52)
+    R = _exp1_inputs(rng, 60)
+    M = 10.0 ** rng.uniform(-1, 1, R.shape)
+    for r, m in zip(R, M):
+        u = OC.exp1_metric_one(r, m)
+        zs = np.linspace(u[0] - 3, u[0] + 3, 200001)
+        d = m[0] * (zs - r[0]) ** 2 + m[2] * (np.exp(zs) - r[2]) ** 2
+        best = float(d.min())
+        du = m[0] * (u[0] - r[0]) ** 2 + m[2] * (u[2] - r[2]) ** 2
+        if math.exp(r[0]) > r[2]:
+            assert du <= best * (1 + 1e-9) + 1e-15
+
+
+def test_exp1_support_term_brute_force():
+    """inf over X of <lambda, x> for lambda in Lambda = {a <= 0, c >= 0}:
+    b + a (log(-a/c) - 1), against a grid over the boundary."""
+    from oracle import cones as OC
+    rng = np.random.default_rng(53)
+    for _ in range(50):
+        a, b, c = -rng.uniform(0.1, 3), rng.standard_normal(), rng.uniform(0.1, 3)
+        lam, term = OC.exp1_dual_terms(a, b, c)
+        assert lam == (a, b, c)
+        zs = np.linspace(-20, 10, 300001)
+        grid = b + float(np.min(a * zs + c * np.exp(zs)))
+        # the grid (spacing 1e-4) misses the minimum by O(c e^z spacing^2)
+        assert term <= grid + 1e-12 and grid - term <= 1e-7 * (1 + abs(term))
+    assert OC.exp1_dual_terms(0.5, 1.5, 2.0)[1] == 1.5           # lambda_a = 0: z -> -inf
+    assert OC.exp1_dual_terms(-1.0, 0.0, -1.0)[1] == -math.inf   # lambda_c = 0 < -lambda_a

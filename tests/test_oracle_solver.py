@@ -391,3 +391,15 @@ def test_fisher_small_solves():
     e = bi.size
     spend = np.bincount(bi, weights=prices[gj] * r.x[:e], minlength=30) + r.x[e:e + 30]
     np.testing.assert_allclose(spend, p.meta["w"], rtol=1e-3, atol=1e-3)
+
+
+def test_fisher_fixed_middle_equals_row_form():
+    """The Fisher market with exponential blocks whose middle coordinate is
+    fixed at one by the set and with an explicit row s_i = 1 are the same
+    problem: equal optimal objective and equilibrium prices."""
+    ps = [synth.fisher(seed=1, n_buyers=40, n_goods=16, density=0.3, graph_seed=1, dist="paper", middle=m)
+          for m in ("row", "fixed")]
+    rs = [pdhg.solve(p, pdhg.Settings(tol=1e-8, max_iter=400000)) for p in ps]
+    assert rs[0].status == rs[1].status == "OPTIMAL"
+    assert rs[1].kkt["primal_obj"] == pytest.approx(rs[0].kkt["primal_obj"], rel=1e-6)
+    np.testing.assert_allclose(-rs[1].y[:16], -rs[0].y[:16], rtol=1e-4, atol=1e-6)
