@@ -748,12 +748,27 @@ class Projector:
     Euclidean formula (valid when m is constant on the block, since
     Pi^{cI} = Pi^I).  Box blocks [lo_i, hi_i] (the box set of
     eq. solver-input) clamp, in any diagonal metric; lo and hi have length n
-    and are read at the box coordinates."""
+    and are read at the box coordinates.
 
-    def __init__(self, cones, n, lo=None, hi=None, kappa=None):
+    cone_scale (length n, positive; rescaled-cone mode of Section "Problem
+    Rescaling"): each SOC, RSOC, EXP and POW block j is the scaled set S_j K_j
+    with S_j = diag(cone_scale on the block).  Substituting w = S_j u in
+    min_{w in S_j K_j} ||w - r||_M^2 gives
+        Pi^M_{S_j K_j}(r) = S_j Pi^{S_j M S_j}_{K_j}(S_j^-1 r),
+    the metric form of eq. scaling-induced-metric; the block is projected
+    that way, always with the metric routines (S_j M S_j is diagonal and in
+    general not constant on the block, so ``euclid`` does not apply)."""
+
+    def __init__(self, cones, n, lo=None, hi=None, kappa=None, cone_scale=None):
         self.cones = list(cones)
         self.n = n
         self.groups = {}
+        self.cone_scale = None
+        if cone_scale is not None:
+            self.cone_scale = np.asarray(cone_scale, dtype=float)
+            sc = [np.arange(st, st + d) for kind, st, d, al in self.cones
+                  if kind in ("soc", "rsoc", "exp", "pow")]
+            self.scaled_idx = np.concatenate(sc) if sc else np.zeros(0, dtype=np.int64)
         # exp1 blocks in scaled coordinates: the set kappa X with kappa the
         # block's (common) scale factor; 1 in the original coordinates
         self.kappa = None if kappa is None else np.asarray(kappa, dtype=float)
@@ -784,6 +799,29 @@ class Projector:
         return out
 
     def project(self, r, m=None, euclid=None):
+        r = np.asarray(r, dtype=float)
+        if self.cone_scale is not None and self.scaled_idx.size:
+            idx = self.scaled_idx
+            s = self.cone_scale
+            if euclid is None:
+                euclid = np.ones(len(self.cones), dtype=bool) if m is None else \
+                    np.zeros(len(self.cones), dtype=bool)
+            base = np.ones(self.n) if m is None else np.array(m, dtype=float)
+            for bi, (kind, st, d, al) in enumerate(self.cones):
+                if euclid[bi]:
+                    base[st:st + d] = 1.0
+            r2 = r.copy()
+            r2[idx] = r[idx] / s[idx]
+            m2 = base.copy()
+            m2[idx] = base[idx] * s[idx] * s[idx]
+            out = self._project(r2, m2, np.where(
+                [k in ("soc", "rsoc", "exp", "pow") for k, _, _, _ in self.cones], False, euclid))
+            res = self._project(r, m, euclid)
+            res[idx] = s[idx] * out[idx]
+            return res
+        return self._project(r, m, euclid)
+
+    def _project(self, r, m=None, euclid=None):
         r = np.asarray(r, dtype=float)
         out = r.copy()
         if self.nonneg_idx.size:

@@ -107,6 +107,7 @@ class Settings:
     pock_chambolle: bool = True
     bound_objective: bool = True
     scaling: bool = True
+    cone_scaling: str = "block"   # "block" (cone-preserving) | "rescaled" (rescaled-cone)
     power_iters: int = 128
     a_norm: float = 0.0           # >0 overrides the power iteration
     omega0: float = 0.0           # >0 overrides the initial primal weight
@@ -240,9 +241,14 @@ def setup(prob, st: Settings = None):
     st = st or Settings()
     sc = scale_problem(prob, ruiz_iters=st.ruiz_iters, pc_alpha=st.pc_alpha,
                        pock_chambolle=st.pock_chambolle,
-                       bound_objective=st.bound_objective, enabled=st.scaling)
+                       bound_objective=st.bound_objective, enabled=st.scaling,
+                       cone_mode=st.cone_scaling)
     q = QOp(sc.P, sc.R, sc.D, prob.n)
-    proj = Projector(prob.cones, prob.n, sc.xlo, sc.xhi, kappa=sc.Sx / sc.nu_b)
+    # rescaled-cone mode: a cone block of the scaled problem is S_j K_j
+    # (S_x / nu_b differs from S_x by a positive scalar, which leaves a cone
+    # unchanged)
+    proj = Projector(prob.cones, prob.n, sc.xlo, sc.xhi, kappa=sc.Sx / sc.nu_b,
+                     cone_scale=sc.Sx if st.cone_scaling == "rescaled" else None)
     euclid_blocks = proj.const_blocks(q.diag)
     a_norm = st.a_norm if st.a_norm > 0 else power_norm(sc.A, st.power_iters)
     if not a_norm > 0:       # A = 0 or no rows: any step size keeps tau sigma ||A||^2 < 1

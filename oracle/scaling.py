@@ -32,6 +32,13 @@ combined bound of each row (its value for an equality, else the larger
 finite endpoint in magnitude, 0 when neither is finite): "the bound data" of
 the bound-objective rescaling.
 
+Rescaled-cone mode (cone_mode="rescaled"): the candidates of
+eq. cone-scaling-candidates stay coordinatewise on SOC, RSOC, EXP and POW
+blocks too, so a block becomes S_j K_j with S_j the block's slice of S_x
+(projected through eq. scaling-induced-metric, see cones.Projector).
+Reading: fixed-middle exp1 blocks keep one common factor in both modes, since
+their set is not a cone and S_j X is not a scaled copy of X.
+
 Pins: hand-derived worked examples of one and two Ruiz passes, of a
 Pock-Chambolle pass with alpha = 1 and alpha = 2, of Ruiz followed by
 Pock-Chambolle and of the bound-objective constants
@@ -79,10 +86,14 @@ class Scaled:
         return y / (self.Sy * self.nu_c)
 
 
-def _cone_blocks(cones):
+def _cone_blocks(cones, cone_mode="block"):
+    """Blocks whose coordinates share one factor: every non-elementwise block
+    in the cone-preserving mode, only the exp1 blocks in the rescaled-cone
+    mode (one common factor keeps the set's shape, so a scaled exp1 block is
+    kappa X with kappa = S_x / nu_b)."""
+    if cone_mode == "rescaled":
+        return [(st, d) for kind, st, d, al in cones if kind == "exp1"]
     return [(st, d) for kind, st, d, al in cones if kind not in ("free", "nonneg", "box")]
-# (exp1 blocks are cone blocks here: one common factor keeps the set's
-# shape, so the scaled block is kappa X with kappa = S_x / nu_b)
 
 
 def combined_bounds(lo, hi):
@@ -106,12 +117,14 @@ def _abs_power_sums(A, e):
 
 
 def scale_problem(prob, ruiz_iters=10, pc_alpha=1.0, pock_chambolle=True,
-                  bound_objective=True, enabled=True):
+                  bound_objective=True, enabled=True, cone_mode="block"):
+    if cone_mode not in ("block", "rescaled"):
+        raise ValueError(cone_mode)
     A = sp.csr_matrix(prob.A, dtype=float, copy=True)
     m, n = A.shape
     Sx = np.ones(n)
     Sy = np.ones(m)
-    blocks = _cone_blocks(prob.cones)
+    blocks = _cone_blocks(prob.cones, cone_mode)
     if enabled and m > 0:        # no rows: every factor is 1
         for _ in range(ruiz_iters):
             absA = abs(A)
