@@ -508,6 +508,71 @@ def bench_fisher_paper(args):
     return out
 
 
+# the ablation variants: settings on top of the defaults (reflected Halpern,
+# Jacobi inner metric, monotone adaptive inner tolerance, cone-preserving
+# block scaling)
+ABLATION_VARIANTS = [
+    ("default", {}),
+    ("no_jacobi", {"inner": "euclid"}),
+    ("fixed_eps_in_1e-6", {"eps_in0": 1e-6, "eps_min": 1e-6}),
+    ("fixed_eps_in_1e-9", {"eps_in0": 1e-9, "eps_min": 1e-9}),
+    ("averaged", {"scheme": "avg"}),
+    ("rescaled_cone", {"cone_scaling": "rescaled"}),
+]
+
+
+def sgm(values, shift=10.0):
+    """Shifted geometric mean with shift 10."""
+    v = np.asarray(values, dtype=float)
+    return float(np.exp(np.mean(np.log(v + shift))) - shift)
+
+
+def bench_ablation(args):
+    """Synthetic analogue of the paper's inner-accuracy ablation (App.
+    "Ablation: Inner Accuracy and Preconditioning"), widened to the averaged
+    scheme and the rescaled-cone mode: every variant solves the ten tiny QPs
+    (seeds 0-9, sparse general Q) and the mixed-cone instance (diagonal plus
+    low-rank Q) to --tol from a cold start, with a --time-limit per solve.
+    Reported per variant and family: solved count, SGM10 of solve time and
+    of outer iterations, total inner steps."""
+    import torch
+    import paper_2608_09159_amd as pkg
+    from instances import synth
+    families = [("tiny QP n=200 m=100 (seeds 0-9)", [synth.tiny_qp(s) for s in range(10)]),
+                ("mixed-cone SOCP/QCQP n=1e5 m=5e4", [synth.mixed_cone(seed=0)])]
+    out = {"workload": "ablation", "tol": args.tol, "time_limit_s": args.time_limit, "families": {}}
+    stream = torch.cuda.current_stream()
+    for fname, probs in families:
+        h = pkg.setup(probs[0], tol=args.tol, stream=stream.cuda_stream)
+        h.solve()                             # first-launch costs, outside the timings
+        h.free()
+        rows = {}
+        for vname, kw in ABLATION_VARIANTS:
+            times, its, inner, solved = [], [], 0, 0
+            for p in probs:
+                h = pkg.setup(p, tol=args.tol, time_limit=args.time_limit, max_iter=10_000_000,
+                              stream=stream.cuda_stream, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = h.solve()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                h.free()
+                solved += r["status"] == "OPTIMAL"
+                times.append(dt if r["status"] == "OPTIMAL" else args.time_limit)
+                its.append(r["iterations"])
+                inner += r["inner_iterations"]
+                if dt > 2.0:
+                    log(f"  {p.name} {vname}: {r['status']} {r['iterations']} it in {dt:.1f} s")
+            rows[vname] = {"solved": solved, "of": len(probs), "time_sgm10_s": sgm(times),
+                           "iter_sgm10": sgm(its), "inner_total": int(inner), "settings": kw}
+            log(f"ablation {fname} {vname}: {solved}/{len(probs)} solved, "
+                f"SGM10 {rows[vname]['time_sgm10_s']:.4f} s, {rows[vname]['iter_sgm10']:.0f} it, "
+                f"{inner} inner")
+        out["families"][fname] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,6 +597,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=100, help="fisher_warm: training epochs")
     ap.add_argument("--lr", type=float, default=1e-4, help="fisher_warm: Adam learning rate")
     ap.add_argument("--buyers", type=int, default=100_000, help="fisher_paper: buyer count")
+    ap.add_argument("--time-limit", type=float, default=20.0, help="ablation: seconds per solve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -563,6 +629,9 @@ def main():
         return
     if args.workload == "fisher_paper":
         print(json.dumps(bench_fisher_paper(args)), flush=True)
+        return
+    if args.workload == "ablation":
+        print(json.dumps(bench_ablation(args)), flush=True)
         return
     prob, wname = workload(args.workload)
     if args.workload == "portfolio_batch":

@@ -22,10 +22,17 @@
  * candidate.
  *
  * Conventions
- *  - All pointers in pdhcg_problem and the x0/y0/x/y/s arguments are HOST
- *    pointers.  The library deep-copies problem data during setup; the caller
- *    keeps ownership of every buffer it passes and may free it after the call
- *    returns.  Handles are opaque, owned by the library, freed by pdhcg_free.
+ *  - settings.memory_kind says where the caller's arrays live: with
+ *    PDHCG_MEM_HOST (default) every pointer of pdhcg_problem and the
+ *    x0/y0/x/y/s arguments of the solve calls is a host pointer; with
+ *    PDHCG_MEM_DEVICE each is a device pointer on the current device (the
+ *    data of torch CUDA tensors, say).  The library deep-copies problem data
+ *    during setup; the caller keeps ownership of every buffer it passes and
+ *    may free it after the call returns.  Handles (pdhcg_handle) are opaque,
+ *    owned by the library, freed by pdhcg_free.
+ *  - Device memory of a handle comes from hipMalloc, or from the caller's
+ *    allocator when settings.dev_alloc / dev_free are set (a caching
+ *    allocator such as torch's).
  *  - Matrices are CSR with int64 row pointers (length rows+1, starting at 0,
  *    nondecreasing) and int32 column indices in [0, cols); duplicates are
  *    summed; columns need not be sorted.
@@ -40,6 +47,7 @@
 #ifndef PDHCG_H
 #define PDHCG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -83,10 +91,21 @@ extern "C" {
                                  Equilibrium"); a convex set, not a cone    */
 
 /* ---- enumerations in settings ---------------------------------------- */
+#define PDHCG_MEM_HOST    0   /* caller arrays are host memory                */
+#define PDHCG_MEM_DEVICE  1   /* caller arrays are device memory              */
 #define PDHCG_SCHEME_RH   0   /* reflected-Halpern epochs (eq. rh-update)     */
 #define PDHCG_SCHEME_AVG  1   /* averaged epochs of Alg. 1                    */
 #define PDHCG_INNER_JACOBI 0  /* eq. jacobi-bb-step                           */
 #define PDHCG_INNER_EUCLID 1  /* eq. bb-step                                  */
+#define PDHCG_SCALE_BLOCK 0   /* cone-preserving block scaling
+                                 (eq. cone-preserving-scaling): one common
+                                 factor per cone block, S_j K_j = K_j       */
+#define PDHCG_SCALE_CONE  1   /* rescaled-cone mode: coordinatewise factors
+                                 (eq. cone-scaling-candidates) on SOC, RSOC,
+                                 EXP and POW blocks, which become S_j K_j
+                                 and are projected through
+                                 eq. scaling-induced-metric; EXP1 blocks keep
+                                 one common factor (their set is not a cone)*/
 #define PDHCG_PREC_FP64   0
 #define PDHCG_PREC_FP32   1   /* FP32 copies of A, A^T, P, R for the bulk
                                  sweeps (A^T y, P u, R u, A w; FP32 products
@@ -131,6 +150,13 @@ typedef struct {
     const double*  x_lo;
     const double*  x_hi;
 } pdhcg_problem;
+
+typedef void* (*pdhcg_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*pdhcg_free_fn)(void* ptr, void* stream, void* ctx);
+
+/* Opaque solver handle: the scaled instances on the device, their step
+ * sizes and solver state.                                                   */
+typedef struct pdhcg_handle pdhcg_handle;
 
 typedef struct {
     /* termination */
@@ -193,6 +219,19 @@ typedef struct {
                                      of work (inputs, outputs, traces and
                                      scalings stay in the caller's order);
                                      0 (default): the caller's order         */
+    int32_t cone_scaling;         /* PDHCG_SCALE_* (default BLOCK)            */
+    int32_t memory_kind;          /* PDHCG_MEM_* of the caller's problem
+                                     arrays, warm starts and outputs
+                                     (default HOST)                           */
+    /* device allocator (both or neither; default NULL = hipMalloc/hipFree):
+     * dev_alloc(bytes, stream, ctx) returns device memory on the current
+     * device usable on `stream` (settings.stream) or NULL on failure
+     * (PDHCG_E_MEM); dev_free(ptr, stream, ctx) releases it.  Called during
+     * pdhcg_setup, the solve calls (buffers created on first use) and
+     * pdhcg_free, on the calling thread.                                    */
+    pdhcg_alloc_fn dev_alloc;
+    pdhcg_free_fn  dev_free;
+    void*          alloc_ctx;
 } pdhcg_settings;
 
 typedef struct {
@@ -205,8 +244,9 @@ typedef struct {
     double  setup_s, solve_s;
     double  omega;                /* final primal weight                      */
     double  a_norm;               /* ||A^||_2 used for the step size          */
-    /* caller-allocated host outputs, nullable: x[n], y[m], s[n] (dual slack
-       s = Qx + c - A^T y of the original problem)                            */
+    /* caller-allocated outputs (host or device memory per
+       settings.memory_kind), nullable: x[n], y[m], s[n] (dual slack
+       s = Qx + c - A^T y of the original problem at the returned x, y)      */
     double* x;
     double* y;
     double* s;
@@ -242,13 +282,22 @@ int pdhcg_default_settings(pdhcg_settings* s);
  * to the current HIP device and return a handle in *out.  count > 1 prepares
  * a batch for pdhcg_solve_batch.  On error *out is left NULL.               */
 int pdhcg_setup(const pdhcg_problem* probs, int32_t count,
-                const pdhcg_settings* s, void** out);
+                const pdhcg_settings* s, pdhcg_handle** out);
 
-/* Solve the single problem of handle h (count == 1) from the optional warm
- * start (x0[n], y0[m], original space; NULL means zero).  Fills *res
- * (status, counters, residuals, objectives, timings) and, when non-NULL,
- * res->x, res->y, res->s.  Returns PDHCG_E_STATE for a batch handle.        */
-int pdhcg_solve(void* h, const double* x0, const double* y0, pdhcg_result* res);
+/* Solve the single problem of handle h (count == 1) with the restarted
+ * PDHG method of the implementation section: evaluations of the PDHG
+ * operator (eq. theory-pdhg-map) whose primal step is the conic proximal
+ * subproblem (eq. prox-subproblem), reflected-Halpern epochs (eq. rh-update;
+ * or averaged epochs of Alg. 1 with settings.scheme), adaptive restarts
+ * (eq. practical-restart-rule) with the PID primal weight (eq. pid-weight),
+ * until the relative KKT residuals of the unscaled candidate (eq. kkt-cqp)
+ * are within settings.tol, or max_iter / time_limit.  Starts from the
+ * optional warm start (x0[n], y0[m], original space, memory_kind memory;
+ * NULL means zero).  Fills *res (status, counters, residuals, objectives,
+ * timings) and, when non-NULL, res->x, res->y and the dual slack res->s,
+ * all computed on the device.  Returns PDHCG_E_STATE for a batch handle,
+ * PDHCG_E_HIP when a device call fails (status is then unset).             */
+int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, pdhcg_result* res);
 
 /* Solve every problem of a batch handle (count > 1 at setup) in one
  * persistent launch, replayed from a HIP graph: each workgroup takes the next
@@ -257,21 +306,21 @@ int pdhcg_solve(void* h, const double* x0, const double* y0, pdhcg_result* res);
  * restarts and inner tolerance, then takes the next.  Every instance runs to
  * its own termination (tol, max_iter); settings.time_limit bounds the whole
  * launch (instances still running then report PDHCG_TIME_LIMIT).
- * x0s/y0s: NULL or arrays of `count` host pointers (each may be NULL; original
- * space).  res: array of `count` results; their x/y/s pointers may be set.
+ * x0s/y0s: NULL or host arrays of `count` pointers (each may be NULL;
+ * original space; each pointing to memory_kind memory).  res: array of `count` results; their x/y/s pointers may be set.
  * kernel_s of res[0] holds the device time of the launch; setup_s and
  * solve_s are those of the whole batch.  For a single-problem handle this is
  * pdhcg_solve on res[0].                                                     */
-int pdhcg_solve_batch(void* h, const double* const* x0s, const double* const* y0s,
+int pdhcg_solve_batch(pdhcg_handle* h, const double* const* x0s, const double* const* y0s,
                       pdhcg_result* res);
 
 /* Copy the recorded iterations of instance `inst` into *t.  Requires
  * settings.trace_iters > 0 at setup; PDHCG_E_NOTRACE otherwise.             */
-int pdhcg_get_trace(void* h, int32_t inst, pdhcg_trace* t);
+int pdhcg_get_trace(pdhcg_handle* h, int32_t inst, pdhcg_trace* t);
 
 /* Copy the scaling of instance `inst`: Sx[n], Sy[m] (nullable) and the
  * bound/objective factors nu_b, nu_c (nullable); also eta and omega0.       */
-int pdhcg_get_scaling(void* h, int32_t inst, double* Sx, double* Sy,
+int pdhcg_get_scaling(pdhcg_handle* h, int32_t inst, double* Sx, double* Sy,
                       double* nu_b, double* nu_c, double* eta, double* omega0);
 
 /* Diagnostics of a PDHCG_NUMERICAL status on the current device: *count =
@@ -319,7 +368,7 @@ int pdhcg_project_cones_noalloc(int32_t type, int32_t dim, int64_t count, const 
                                 const double* r, const double* metric, double* out, void* stream);
 
 /* Release every host and device resource of h (NULL is a no-op).          */
-void pdhcg_free(void* h);
+void pdhcg_free(pdhcg_handle* h);
 
 /* Static description of an error code or status.                          */
 const char* pdhcg_strerror(int code);

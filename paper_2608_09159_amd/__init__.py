@@ -26,11 +26,18 @@ Functions mirror the C ABI of ``include/pdhcg.h``:
 (n, m, A as scipy CSR, b, c, optional P / R / D, cones as
 (type, start, dim, alpha) tuples with type in CONE_CODES, optional row
 bounds row_lo / row_hi and box bounds x_lo / x_hi).
+
+``memory_kind="device"`` passes every problem array, warm start and output
+to the library as device memory (torch CUDA tensors; numpy inputs are moved
+to the device first) and returns x, y, s as torch CUDA tensors;
+``allocator="torch"`` makes the library take its device memory from torch's
+caching allocator (settings.dev_alloc / dev_free).
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -42,6 +49,8 @@ STATUS = {1: "OPTIMAL", 2: "MAX_ITER", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "ABOR
 SCHEMES = {"rh": 0, "avg": 1}
 INNER = {"jacobi": 0, "euclid": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
+CONE_SCALING = {"block": 0, "rescaled": 1}
+MEMORY_KIND = {"host": 0, "device": 1}
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -57,6 +66,28 @@ class ProblemC(C.Structure):
                 ("nblocks", C.c_int32), ("cone_type", _i32p), ("cone_start", _i32p),
                 ("cone_dim", _i32p), ("cone_alpha", _dp),
                 ("row_lo", _dp), ("row_hi", _dp), ("x_lo", _dp), ("x_hi", _dp)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None                      # NULL: the library reports PDHCG_E_MEM
+
+
+def _torch_free(ptr, stream, ctx):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# module-level, so the callbacks outlive every handle that uses them
+TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+TORCH_FREE = _FREE_FN(_torch_free)
 
 
 class Settings(C.Structure):
@@ -75,7 +106,9 @@ class Settings(C.Structure):
                 ("host_poll", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
                 ("tune_iters", C.c_int32), ("fp32_tol", C.c_double),
-                ("interleave", C.c_int32)]
+                ("interleave", C.c_int32), ("cone_scaling", C.c_int32),
+                ("memory_kind", C.c_int32), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class ResultC(C.Structure):
@@ -179,6 +212,16 @@ def default_settings(**kw) -> Settings:
             v = INNER[v] if isinstance(v, str) else v
         elif k == "precision":
             v = PRECISION[v] if isinstance(v, str) else v
+        elif k == "cone_scaling":
+            v = CONE_SCALING[v] if isinstance(v, str) else v
+        elif k == "memory_kind":
+            v = MEMORY_KIND[v] if isinstance(v, str) else v
+        elif k == "allocator":
+            if v == "torch":
+                s.dev_alloc, s.dev_free = TORCH_ALLOC, TORCH_FREE
+            elif v is not None:
+                raise ValueError(f"allocator {v!r}: 'torch' or None")
+            continue
         elif k == "stream":
             v = getattr(v, "cuda_stream", v)
         if not hasattr(s, k):
@@ -188,20 +231,42 @@ def default_settings(**kw) -> Settings:
 
 
 def _ptr(a, ctype):
-    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):           # a torch tensor: its device address
+        return C.cast(C.c_void_p(a.data_ptr()), C.POINTER(ctype))
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+_TORCH_DT = {np.float64: "float64", np.int64: "int64", np.int32: "int32"}
+
+
+def _on_device(x, dt):
+    """x (numpy array, sequence or torch tensor) as a contiguous torch CUDA
+    tensor of dtype dt."""
+    import torch
+    tdt = getattr(torch, _TORCH_DT[dt])
+    if hasattr(x, "data_ptr"):
+        return x.to(device="cuda", dtype=tdt).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
+
+
+def _is_device(settings):
+    return settings is not None and settings.memory_kind == MEMORY_KIND["device"]
 
 
 class _Marshalled:
-    """Keeps the numpy buffers alive for the duration of pdhcg_setup."""
+    """Keeps the argument buffers alive for the duration of pdhcg_setup
+    (numpy arrays, or torch CUDA tensors with device memory)."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, device=False):
         A = prob.A.tocsr()
         self.keep = []
 
         def arr(x, dt):
             if x is None:
                 return None
-            y = np.ascontiguousarray(x, dtype=dt)
+            y = _on_device(x, dt) if device else np.ascontiguousarray(x, dtype=dt)
             self.keep.append(y)
             return y
 
@@ -245,14 +310,16 @@ class Handle:
     def solve(self, x0=None, y0=None, want_s=False):
         lib = load()
         res = ResultC()
-        x = np.zeros(self.n)
-        y = np.zeros(self.m)
-        s = np.zeros(self.n) if want_s else None
+        dev = _is_device(self.settings)
+        vec = _vec_factory(dev)
+        x = vec(self.n)
+        y = vec(self.m)
+        s = vec(self.n) if want_s else None
         res.x = _ptr(x, C.c_double)
         res.y = _ptr(y, C.c_double)
         res.s = _ptr(s, C.c_double) if want_s else None
-        x0a = np.ascontiguousarray(x0, dtype=np.float64) if x0 is not None else None
-        y0a = np.ascontiguousarray(y0, dtype=np.float64) if y0 is not None else None
+        x0a = _as_input(x0, dev)
+        y0a = _as_input(y0, dev)
         _check(lib.pdhcg_solve(self.ptr, _ptr(x0a, C.c_double), _ptr(y0a, C.c_double),
                                C.byref(res)), "pdhcg_solve")
         return _result_dict(res, x, y, s)
@@ -298,10 +365,27 @@ class Handle:
             self.ptr = None
 
     def __del__(self):
+        # at interpreter exit a Python allocator (torch's) may already be
+        # gone: leave the memory to the process end then
+        if sys.is_finalizing() and self.settings is not None and self.settings.dev_free:
+            return
         try:
             self.free()
         except Exception:
             pass
+
+
+def _vec_factory(device):
+    if not device:
+        return lambda k: np.zeros(k)
+    import torch
+    return lambda k: torch.zeros(max(k, 0), dtype=torch.float64, device="cuda")
+
+
+def _as_input(v, device):
+    if v is None:
+        return None
+    return _on_device(v, np.float64) if device else np.ascontiguousarray(v, dtype=np.float64)
 
 
 def _result_dict(res, x, y, s):
@@ -391,9 +475,11 @@ class BatchHandle(Handle):
         x0s / y0s: None or sequences of per-instance arrays (or None)."""
         lib = load()
         res = (ResultC * self.count)()
-        xs = [np.zeros(n) for n in self.ns]
-        ys = [np.zeros(m) for m in self.ms]
-        ss = [np.zeros(n) for n in self.ns] if want_s else [None] * self.count
+        dev = _is_device(self.settings)
+        vec = _vec_factory(dev)
+        xs = [vec(n) for n in self.ns]
+        ys = [vec(m) for m in self.ms]
+        ss = [vec(n) for n in self.ns] if want_s else [None] * self.count
         for i in range(self.count):
             res[i].x = _ptr(xs[i], C.c_double)
             res[i].y = _ptr(ys[i], C.c_double)
@@ -406,7 +492,7 @@ class BatchHandle(Handle):
             arr = (_dp * self.count)()
             for i, v in enumerate(vs):
                 if v is not None:
-                    a = np.ascontiguousarray(v, dtype=np.float64)
+                    a = _as_input(v, dev)
                     keep.append(a)
                     arr[i] = _ptr(a, C.c_double)
             return arr
@@ -423,7 +509,7 @@ def setup_batch(probs, settings=None, **kw) -> BatchHandle:
     if len(probs) < 2:
         raise ValueError("a batch needs at least two problems; use setup() for one")
     s = settings if settings is not None else default_settings(**kw)
-    ms = [_Marshalled(p) for p in probs]
+    ms = [_Marshalled(p, _is_device(s)) for p in probs]
     arr = (ProblemC * len(probs))(*[m.pc for m in ms])
     h = C.c_void_p()
     _check(lib.pdhcg_setup(arr, len(probs), C.byref(s), C.byref(h)), "pdhcg_setup")
@@ -433,7 +519,7 @@ def setup_batch(probs, settings=None, **kw) -> BatchHandle:
 def setup(prob, settings=None, **kw) -> Handle:
     lib = load()
     s = settings if settings is not None else default_settings(**kw)
-    m = _Marshalled(prob)
+    m = _Marshalled(prob, _is_device(s))
     h = C.c_void_p()
     _check(lib.pdhcg_setup(C.byref(m.pc), 1, C.byref(s), C.byref(h)), "pdhcg_setup")
     return Handle(h.value, prob, s)

@@ -19,10 +19,11 @@ using namespace pdhcg;
 
 namespace {
 
-// row bounds, box blocks or fixed-middle EXP blocks: the kernel variant
+// row bounds, box blocks, fixed-middle EXP blocks or the rescaled-cone
+// mode: the kernel variant
 // compiled with that code runs the instance
 bool needs_ext(const HostInstance& H) {
-  if (!H.rlo.empty() || !H.xlo.empty()) return true;
+  if (!H.rlo.empty() || !H.xlo.empty() || H.resc) return true;
   for (const ConeBlock& k : H.cones)
     if (k.type == PDHCG_CONE_EXP1) return true;
   return false;
@@ -32,18 +33,41 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// device allocations of a handle: hipMalloc, or the caller's allocator
+// (settings.dev_alloc / dev_free)
 struct DevBuf {
   std::vector<void*> ptrs;
   hipError_t err = hipSuccess;
-  template <class T>
-  T* alloc(size_t count) {
+  pdhcg_alloc_fn fa = nullptr;
+  pdhcg_free_fn ff = nullptr;
+  void* ctx = nullptr;
+  void* stream = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void use(const pdhcg_settings& s) {
+    fa = s.dev_alloc;
+    ff = s.dev_free;
+    ctx = s.alloc_ctx;
+    stream = s.stream;
+  }
+  void* raw(size_t bytes) {
     if (err != hipSuccess) return nullptr;
     void* p = nullptr;
-    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    err = hipMalloc(&p, bytes);
+    if (fa) {
+      p = fa(bytes, stream, ctx);
+      if (!p) err = hipErrorOutOfMemory;
+    } else {
+      err = hipMalloc(&p, bytes);
+    }
     if (err != hipSuccess) return nullptr;
     ptrs.push_back(p);
-    return (T*)p;
+    return p;
+  }
+  template <class T>
+  T* alloc(size_t count) {
+    return (T*)raw(std::max<size_t>(count, 1) * sizeof(T));
   }
   template <class T>
   T* upload(const std::vector<T>& v) {
@@ -52,7 +76,10 @@ struct DevBuf {
     return p;
   }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+      if (ff) ff(p, stream, ctx);
+      else (void)hipFree(p);
+    }
     ptrs.clear();
   }
 };
@@ -73,11 +100,16 @@ struct Instance {
   long at_cls_seg[6] = {0, 0, 0, 0, 0, 0};
   size_t bar_bytes = 0;
   long n_warm = 0;
+  int* d_perm = nullptr;       // caller index of each internal coordinate (null: same order)
+  double* io = nullptr;        // IO_DOUBLES of scratch for the dual-slack output
 };
 
 struct Batch;
 
-struct Handle {
+}  // namespace
+
+// the opaque handle of the C ABI
+struct pdhcg_handle {
   pdhcg_settings s;
   DevSettings ds;
   std::vector<Instance*> inst;
@@ -87,6 +119,10 @@ struct Handle {
   int rate_khz = 100000;
   Batch* B = nullptr;     // count > 1: the batch arena and its launch state
 };
+
+namespace {
+
+using Handle = pdhcg_handle;
 
 // Batch of independent instances.  All instance data lives in one device
 // arena, each instance in a contiguous 256-byte aligned region; the
@@ -108,6 +144,8 @@ struct Batch {
   double* d_x0 = nullptr;
   double* d_y0 = nullptr;
   double* d_norm = nullptr;
+  double* d_s = nullptr;          // packed dual slacks (host outputs), made on first use
+  double* io = nullptr;           // IO_DOUBLES of scratch for the dual-slack output
   std::vector<long> offx, offy;   // count + 1 prefix sums of n and m
   int grid = 1;
   bool cones = false;             // some instance has SOC/RSOC/EXP/POW blocks
@@ -249,6 +287,7 @@ int upload_instance(Handle* h, Instance* I) {
   P.xlo = H.xlo.empty() ? nullptr : B.upload(H.xlo);
   P.xhi = H.xhi.empty() ? nullptr : B.upload(H.xhi);
   P.ext = needs_ext(H) ? 1 : 0;
+  P.resc = H.resc ? 1 : 0;
   I->qmax = 0.0;
   for (double q : H.qdiag) I->qmax = std::max(I->qmax, q);
 
@@ -589,6 +628,8 @@ int upload_instance(Handle* h, Instance* I) {
   V.partials = B.alloc<double>((size_t)SL_COUNT * G);
   I->bar_bytes = sizeof(Barrier) + sizeof(unsigned) * (size_t)G * BAR_STRIDE;
   I->bar = (Barrier*)B.alloc<char>(I->bar_bytes);
+  I->d_perm = H.perm.empty() ? nullptr : B.upload(H.perm);
+  I->io = B.alloc<double>(IO_DOUBLES);
   if (B.err != hipSuccess) return PDHCG_E_MEM;
   return PDHCG_OK;
 }
@@ -661,7 +702,61 @@ void report_phases(const unsigned long long* dpt, int grid) {
   }
 }
 
-// unscaled outputs and counters of one solved instance
+// a host copy of a problem whose arrays are device memory
+// (settings.memory_kind = PDHCG_MEM_DEVICE); setup then proceeds as for host
+// input
+struct HostMirror {
+  std::vector<int64_t> arp, prp;
+  std::vector<int32_t> acol, pcol, ctype, cstart, cdim;
+  std::vector<double> aval, b, c, pval, R, D, calpha, rlo, rhi, xlo, xhi;
+  pdhcg_problem p{};
+};
+
+template <class T>
+int d2h(const T* src, int64_t count, std::vector<T>& dst, const T** out) {
+  *out = nullptr;
+  if (!src) return PDHCG_OK;
+  if (count < 0) return PDHCG_E_SHAPE;
+  dst.resize((size_t)std::max<int64_t>(count, 1));
+  if (count > 0 && hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+    return PDHCG_E_HIP;
+  *out = dst.data();
+  return PDHCG_OK;
+}
+
+int mirror_problem(const pdhcg_problem& d, HostMirror& M) {
+  M.p = d;
+  const int64_t n = d.n, m = d.m, r = d.r;
+  if (n < 1 || m < 0 || r < 0 || d.nblocks < 0) return PDHCG_E_SHAPE;
+  constexpr int64_t kMaxNnz = (int64_t)1 << 36;
+  int rc = d2h(d.A_rowptr, m + 1, M.arp, &M.p.A_rowptr);
+  const int64_t nnz = (rc == PDHCG_OK && M.p.A_rowptr) ? M.arp[m] : 0;
+  if (nnz < 0 || nnz > kMaxNnz) return PDHCG_E_CSR;
+  if (rc == PDHCG_OK) rc = d2h(d.A_col, nnz, M.acol, &M.p.A_col);
+  if (rc == PDHCG_OK) rc = d2h(d.A_val, nnz, M.aval, &M.p.A_val);
+  if (rc == PDHCG_OK) rc = d2h(d.b, m, M.b, &M.p.b);
+  if (rc == PDHCG_OK) rc = d2h(d.c, n, M.c, &M.p.c);
+  if (rc == PDHCG_OK) rc = d2h(d.P_rowptr, n + 1, M.prp, &M.p.P_rowptr);
+  const int64_t pnnz = (rc == PDHCG_OK && M.p.P_rowptr) ? M.prp[n] : 0;
+  if (pnnz < 0 || pnnz > kMaxNnz) return PDHCG_E_CSR;
+  if (rc == PDHCG_OK) rc = d2h(d.P_col, pnnz, M.pcol, &M.p.P_col);
+  if (rc == PDHCG_OK) rc = d2h(d.P_val, pnnz, M.pval, &M.p.P_val);
+  if (rc == PDHCG_OK) rc = d2h(d.R, r * n, M.R, &M.p.R);
+  if (rc == PDHCG_OK) rc = d2h(d.D, r * r, M.D, &M.p.D);
+  if (rc == PDHCG_OK) rc = d2h(d.cone_type, (int64_t)d.nblocks, M.ctype, &M.p.cone_type);
+  if (rc == PDHCG_OK) rc = d2h(d.cone_start, (int64_t)d.nblocks, M.cstart, &M.p.cone_start);
+  if (rc == PDHCG_OK) rc = d2h(d.cone_dim, (int64_t)d.nblocks, M.cdim, &M.p.cone_dim);
+  if (rc == PDHCG_OK) rc = d2h(d.cone_alpha, (int64_t)d.nblocks, M.calpha, &M.p.cone_alpha);
+  if (rc == PDHCG_OK) rc = d2h(d.row_lo, m, M.rlo, &M.p.row_lo);
+  if (rc == PDHCG_OK) rc = d2h(d.row_hi, m, M.rhi, &M.p.row_hi);
+  if (rc == PDHCG_OK) rc = d2h(d.x_lo, n, M.xlo, &M.p.x_lo);
+  if (rc == PDHCG_OK) rc = d2h(d.x_hi, n, M.xhi, &M.p.x_hi);
+  return rc;
+}
+
+// counters of one solved instance and, with host outputs (wx, wy non-null:
+// the scaled candidate on the host), the unscaled x and y; the dual slack
+// and device outputs are written by the io kernels
 void finish_result(const HostInstance& H, const Ctl& c, int status, const double* wx, const double* wy,
                    double eta, double setup_s, pdhcg_result* res) {
   const long n = H.n, m = H.m;
@@ -678,31 +773,30 @@ void finish_result(const HostInstance& H, const Ctl& c, int status, const double
   res->a_norm = 0.998 / eta;
   res->setup_s = setup_s;
   const bool pm = !H.perm.empty();   // internal coordinate j is the caller's perm[j]
-  if (res->x)
+  if (res->x && wx)
     for (long i = 0; i < n; ++i) res->x[pm ? H.perm[i] : i] = H.nu_b * wx[i] / H.Sx[i];
-  if (res->y)
+  if (res->y && wy)
     for (long l = 0; l < m; ++l) res->y[l] = H.nu_c * H.Sy[l] * wy[l];
-  if (res->s) {
-    // s = nu_c S_x (Q^ w + c^ - A^T w_y)
-    std::vector<double> q(n, 0.0);
-    if (H.P.rows > 0)
-      for (long i = 0; i < n; ++i)
-        for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) q[i] += H.P.val[k] * wx[H.P.col[k]];
-    if (H.r > 0) {
-      std::vector<double> hh(H.r, 0.0), ht(H.r, 0.0);
-      for (int k = 0; k < H.r; ++k)
-        for (long i = 0; i < n; ++i) hh[k] += H.R[(size_t)k * n + i] * wx[i];
-      for (int k = 0; k < H.r; ++k)
-        for (int b = 0; b < H.r; ++b) ht[k] += H.D[k * H.r + b] * hh[b];
-      for (long i = 0; i < n; ++i)
-        for (int k = 0; k < H.r; ++k) q[i] += H.R[(size_t)k * n + i] * ht[k];
-    }
-    for (long i = 0; i < n; ++i) {
-      double aty = 0.0;
-      for (int64_t k = H.AT.ptr[i]; k < H.AT.ptr[i + 1]; ++k) aty += H.AT.val[k] * wy[H.AT.col[k]];
-      res->s[pm ? H.perm[i] : i] = H.nu_c * H.Sx[i] * (q[i] + H.c[i] - aty);
-    }
+}
+
+// outputs of one instance from its scaled candidate (W, Wy) on the device:
+// with device outputs x, y and s straight into the caller's buffers; with
+// host outputs s through the staging vector `stage` (n doubles), x and y
+// being unscaled on the host by finish_result
+hipError_t device_outputs(const DevProblem& P, const int* perm, double* io, const double* W, const double* Wy,
+                          bool dev, double* stage, pdhcg_result* res, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (dev) {
+    if (res->x) e = launch_scale_out(W, perm, P.Sx, P.nu_b, true, res->x, P.n, st);
+    if (e == hipSuccess && res->y) e = launch_scale_out(Wy, nullptr, P.Sy, P.nu_c, false, res->y, P.m, st);
+    if (e == hipSuccess && res->s) e = launch_dual_slack(P, W, Wy, perm, io, res->s, st);
+    return e;
   }
+  if (res->s) {
+    e = launch_dual_slack(P, W, Wy, perm, io, stage, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(res->s, stage, (size_t)P.n * sizeof(double), hipMemcpyDeviceToHost, st);
+  }
+  return e;
 }
 
 // carves one instance's region of the batch arena: `put` places a host
@@ -776,6 +870,8 @@ void carve_instance(const HostInstance& H, int trace_cap, bool avg, Carve& c, In
   P.xlo = H.xlo.empty() ? nullptr : c.put(H.xlo);
   P.xhi = H.xhi.empty() ? nullptr : c.put(H.xhi);
   P.ext = needs_ext(H) ? 1 : 0;
+  P.resc = H.resc ? 1 : 0;
+  D.perm = H.perm.empty() ? nullptr : c.put(H.perm);
   DevVec& V = D.V;
   V = DevVec{};
   V.x = c.take<double>(n);
@@ -890,6 +986,7 @@ int setup_batch(Handle* h) {
     base[i + 1] = base[i] + ((c.off + 255) & ~(size_t)255);
   }
   B->arena = B->mem.alloc<char>(base[count]);
+  B->io = B->mem.alloc<double>(IO_DOUBLES);
   if (B->mem.err != hipSuccess) return B->mem.err == hipErrorOutOfMemory ? PDHCG_E_MEM : PDHCG_E_HIP;
   {
     std::vector<char> stage;
@@ -1101,6 +1198,7 @@ int pdhcg_default_settings(pdhcg_settings* s) {
   s->tune_iters = 64;
   s->fp32_tol = 0.0;
   s->interleave = 0;
+  s->cone_scaling = PDHCG_SCALE_BLOCK;
   return PDHCG_OK;
 }
 
@@ -1127,7 +1225,7 @@ const char* pdhcg_strerror(int code) {
 
 const char* pdhcg_version(void) { return "pdhcg-mi355x 0.1 (gfx950, FP64)"; }
 
-int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings* s, void** out) {
+int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings* s, pdhcg_handle** out) {
   if (!out) return PDHCG_E_ARG;
   *out = nullptr;
   if (!probs || !s || count < 1) return PDHCG_E_ARG;
@@ -1135,9 +1233,22 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
       !(s->rho >= 0.5 && s->rho <= 1.0) || s->power_iters < 0 ||
       (s->scheme != PDHCG_SCHEME_RH && s->scheme != PDHCG_SCHEME_AVG) ||
       (s->scheme == PDHCG_SCHEME_AVG && (s->avg_epoch < 1 || s->precision != PDHCG_PREC_FP64)) ||
-      (s->precision != PDHCG_PREC_FP64 && s->precision != PDHCG_PREC_FP32) || s->trace_iters < 0)
+      (s->precision != PDHCG_PREC_FP64 && s->precision != PDHCG_PREC_FP32) || s->trace_iters < 0 ||
+      (s->cone_scaling != PDHCG_SCALE_BLOCK && s->cone_scaling != PDHCG_SCALE_CONE))
     return PDHCG_E_ARG;
   if (count > 1 && s->precision != PDHCG_PREC_FP64) return PDHCG_E_ARG;   // batches are FP64
+  if ((s->memory_kind != PDHCG_MEM_HOST && s->memory_kind != PDHCG_MEM_DEVICE) ||
+      (s->dev_alloc == nullptr) != (s->dev_free == nullptr))
+    return PDHCG_E_ARG;
+  // device-resident problem arrays: validated and rescaled from a host copy
+  std::vector<HostMirror> mirror;
+  if (s->memory_kind == PDHCG_MEM_DEVICE) {
+    mirror.resize(count);
+    for (int i = 0; i < count; ++i) {
+      int rc = mirror_problem(probs[i], mirror[i]);
+      if (rc != PDHCG_OK) return rc;
+    }
+  }
   if (s->lanes_at < 0 || s->lanes_at > 64 || (s->lanes_at & (s->lanes_at - 1)) ||
       s->lanes_a < 0 || s->lanes_a > 64 || (s->lanes_a & (s->lanes_a - 1)))
     return PDHCG_E_ARG;
@@ -1153,8 +1264,9 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   for (int i = 0; i < count; ++i) {
     Instance* I = new (std::nothrow) Instance();
     if (!I) { pdhcg_free(h); return PDHCG_E_MEM; }
+    I->mem.use(h->s);
     h->inst.push_back(I);
-    int rc = build_instance(probs[i], h->s, I->H);
+    int rc = build_instance(mirror.empty() ? probs[i] : mirror[i].p, h->s, I->H);
     if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
   }
   int dev = 0, rate_khz = 0;
@@ -1169,6 +1281,7 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   if (count > 1) {
     h->B = new (std::nothrow) Batch();
     if (!h->B) { pdhcg_free(h); return PDHCG_E_MEM; }
+    h->B->mem.use(h->s);
     h->B->count = count;
     int rc = setup_batch(h);
     if (rc != PDHCG_OK) { pdhcg_free(h); return rc; }
@@ -1199,8 +1312,7 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
   return PDHCG_OK;
 }
 
-int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res) {
-  Handle* h = (Handle*)hv;
+int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, pdhcg_result* res) {
   if (!h || !res) return PDHCG_E_ARG;
   if (h->inst.size() != 1 || h->B) return PDHCG_E_STATE;
   Instance* I = h->inst[0];
@@ -1209,8 +1321,11 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   hipStream_t st = h->stream;
   double t0 = now_s();
   // warm start in the scaled space: x^ = S_x x0 / nu_b, y^ = y0 / (nu_c S_y)
+  const bool dev = h->s.memory_kind == PDHCG_MEM_DEVICE;
   std::vector<double> tmp;
-  if (x0) {
+  if (x0 && dev) {
+    HIPCHK(launch_scale_in(x0, I->d_perm, I->P.Sx, H.nu_b, false, I->V.zb, n, st));
+  } else if (x0) {
     tmp.resize(n);
     for (long i = 0; i < n; ++i) tmp[i] = H.Sx[i] * x0[H.perm.empty() ? i : H.perm[i]] / H.nu_b;
     HIPCHK(hipMemcpyAsync(I->V.zb, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1218,7 +1333,9 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
     HIPCHK(launch_fill(I->V.zb, n, 0.0, st));
   }
   std::vector<double> tmpy;
-  if (y0 && m > 0) {
+  if (y0 && m > 0 && dev) {
+    HIPCHK(launch_scale_in(y0, nullptr, I->P.Sy, H.nu_c, true, I->V.y, m, st));
+  } else if (y0 && m > 0) {
     tmpy.resize(m);
     for (long l = 0; l < m; ++l) tmpy[l] = y0[l] / (H.nu_c * H.Sy[l]);
     HIPCHK(hipMemcpyAsync(I->V.y, tmpy.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1243,8 +1360,11 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   a.lds_bytes = I->lds_bytes;
   a.profile = h->s.verbose & 8 ? 1 : 0;
   unsigned long long* dpt = nullptr;
+  DevBuf tbuf;                  // phase timers (settings.verbose & 8)
+  tbuf.use(h->s);
   if (a.profile) {
-    HIPCHK(hipMalloc(&dpt, sizeof(unsigned long long) * PT_COUNT * I->grid));
+    dpt = tbuf.alloc<unsigned long long>((size_t)PT_COUNT * I->grid);
+    if (tbuf.err != hipSuccess) return PDHCG_E_MEM;
     HIPCHK(hipMemsetAsync(dpt, 0, sizeof(unsigned long long) * PT_COUNT * I->grid, st));
   }
   a.ptimes = dpt;
@@ -1322,28 +1442,37 @@ int pdhcg_solve(void* hv, const double* x0, const double* y0, pdhcg_result* res)
   res->polish_iterations = switch_at >= 0 ? c.ktot - switch_at : 0;
   if (h->s.verbose & 8) {
     report_phases(dpt, I->grid);
-    (void)hipFree(dpt);
+    tbuf.release();
   }
   // results (unscaled): the last PDHG candidate, or for averaged epochs the
   // state, which is the epoch average after the last restart
   const bool avg = h->s.scheme == PDHCG_SCHEME_AVG;
   const double* W = avg ? I->V.x : (I->P.q_diag ? I->V.wx : I->V.u);
   const double* Wy = avg ? I->V.y : I->V.wy;
-  std::vector<double> wx(n), wy(m);
-  if (c.ktot > 0) {
+  if (c.ktot == 0) {   // no evaluation yet: the zero point
+    HIPCHK(launch_fill(I->V.t1, n, 0.0, st));
+    HIPCHK(launch_fill(I->V.Aw, m, 0.0, st));
+    W = I->V.t1;
+    Wy = I->V.Aw;
+  }
+  HIPCHK(device_outputs(I->P, I->d_perm, I->io, W, Wy, dev, I->V.t2, res, st));
+  std::vector<double> wx, wy;
+  if (!dev && (res->x || res->y)) {
+    wx.resize(n);
+    wy.resize(std::max<long>(m, 1));
     HIPCHK(hipMemcpyAsync(wx.data(), W, n * sizeof(double), hipMemcpyDeviceToHost, st));
     if (m > 0) HIPCHK(hipMemcpyAsync(wy.data(), Wy, m * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
   }
-  finish_result(H, c, status, wx.data(), wy.data(), I->P.eta, h->setup_s, res);
+  HIPCHK(hipStreamSynchronize(st));
+  finish_result(H, c, status, wx.empty() ? nullptr : wx.data(), wx.empty() ? nullptr : wy.data(), I->P.eta,
+                h->setup_s, res);
   res->solve_s = now_s() - t0;
   return PDHCG_OK;
 }
 
-int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y0s, pdhcg_result* res) {
-  Handle* h = (Handle*)hv;
+int pdhcg_solve_batch(pdhcg_handle* h, const double* const* x0s, const double* const* y0s, pdhcg_result* res) {
   if (!h || !res) return PDHCG_E_ARG;
-  if (!h->B) return pdhcg_solve(hv, x0s ? x0s[0] : nullptr, y0s ? y0s[0] : nullptr, res);
+  if (!h->B) return pdhcg_solve(h, x0s ? x0s[0] : nullptr, y0s ? y0s[0] : nullptr, res);
   Batch* B = h->B;
   const int count = B->count;
   hipStream_t st = h->stream;
@@ -1351,9 +1480,10 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
   // warm starts: scaled on the host into packed buffers; the reset node of
   // the graph copies them into each instance's zb / y
   bool dirty = false;
+  const bool dev = h->s.memory_kind == PDHCG_MEM_DEVICE;
   std::vector<double> px, py;
-  if (x0s) px.assign(std::max<long>(B->offx[count], 1), 0.0);
-  if (y0s) py.assign(std::max<long>(B->offy[count], 1), 0.0);
+  if (x0s && !dev) px.assign(std::max<long>(B->offx[count], 1), 0.0);
+  if (y0s && !dev) py.assign(std::max<long>(B->offy[count], 1), 0.0);
   if (x0s && !B->d_x0) B->d_x0 = B->mem.alloc<double>(B->offx[count]);
   if (y0s && !B->d_y0) B->d_y0 = B->mem.alloc<double>(std::max<long>(B->offy[count], 1));
   if (B->mem.err != hipSuccess) return PDHCG_E_MEM;
@@ -1361,9 +1491,14 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
     const HostInstance& H = h->inst[i]->H;
     const double* x0 = x0s ? x0s[i] : nullptr;
     const double* y0 = y0s ? y0s[i] : nullptr;
-    if (x0)
+    const DevProblem& P = B->desc[i].P;
+    if (x0 && dev)
+      HIPCHK(launch_scale_in(x0, B->desc[i].perm, P.Sx, H.nu_b, false, B->d_x0 + B->offx[i], H.n, st));
+    else if (x0)
       for (long j = 0; j < H.n; ++j) px[B->offx[i] + j] = H.Sx[j] * x0[H.perm.empty() ? j : H.perm[j]] / H.nu_b;
-    if (y0)
+    if (y0 && dev)
+      HIPCHK(launch_scale_in(y0, nullptr, P.Sy, H.nu_c, true, B->d_y0 + B->offy[i], H.m, st));
+    else if (y0)
       for (long l = 0; l < H.m; ++l) py[B->offy[i] + l] = y0[l] / (H.nu_c * H.Sy[l]);
     const double* want_x = x0 ? B->d_x0 + B->offx[i] : nullptr;
     const double* want_y = (y0 && H.m > 0) ? B->d_y0 + B->offy[i] : nullptr;
@@ -1373,8 +1508,9 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
       dirty = true;
     }
   }
-  if (x0s) HIPCHK(hipMemcpyAsync(B->d_x0, px.data(), sizeof(double) * B->offx[count], hipMemcpyHostToDevice, st));
-  if (y0s && B->offy[count] > 0)
+  if (x0s && !dev)
+    HIPCHK(hipMemcpyAsync(B->d_x0, px.data(), sizeof(double) * B->offx[count], hipMemcpyHostToDevice, st));
+  if (y0s && !dev && B->offy[count] > 0)
     HIPCHK(hipMemcpyAsync(B->d_y0, py.data(), sizeof(double) * B->offy[count], hipMemcpyHostToDevice, st));
   if (dirty) {
     int rc = upload_desc(h, st);
@@ -1391,9 +1527,12 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
     HIPCHK(hipEventRecord(ev0, st));
   }
   unsigned long long* dpt = nullptr;
+  DevBuf tbuf;                  // phase timers (settings.verbose & 8)
+  tbuf.use(h->s);
   if (h->s.verbose & 8) {
     // profiled run: a direct launch with phase timers instead of the graph
-    HIPCHK(hipMalloc(&dpt, sizeof(unsigned long long) * PT_COUNT * B->grid));
+    dpt = tbuf.alloc<unsigned long long>((size_t)PT_COUNT * B->grid);
+    if (tbuf.err != hipSuccess) return PDHCG_E_MEM;
     BatchArgs pa = batch_args(h, h->s.max_iter);
     pa.ptimes = dpt;
     HIPCHK(launch_batch_reset(B->d_desc, B->count, B->d_queue, st));
@@ -1405,11 +1544,34 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
   }
   if (timing) HIPCHK(hipEventRecord(ev1, st));
   std::vector<Ctl> ctl(count);
-  std::vector<double> ox(std::max<long>(B->offx[count], 1)), oy(std::max<long>(B->offy[count], 1));
   HIPCHK(hipMemcpyAsync(ctl.data(), B->d_ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(ox.data(), B->d_outx, sizeof(double) * B->offx[count], hipMemcpyDeviceToHost, st));
-  if (B->offy[count] > 0)
-    HIPCHK(hipMemcpyAsync(oy.data(), B->d_outy, sizeof(double) * B->offy[count], hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // candidates of instances stopped before their first evaluation: the zero
+  // point; then the device outputs (dual slacks through d_s for host
+  // outputs)
+  bool want_s = false;
+  for (int i = 0; i < count; ++i) {
+    if (ctl[i].ktot == 0) {
+      HIPCHK(launch_fill(B->d_outx + B->offx[i], h->inst[i]->H.n, 0.0, st));
+      HIPCHK(launch_fill(B->d_outy + B->offy[i], h->inst[i]->H.m, 0.0, st));
+    }
+    want_s = want_s || res[i].s;
+  }
+  if (want_s && !dev && !B->d_s) {
+    B->d_s = B->mem.alloc<double>(B->offx[count]);
+    if (B->mem.err != hipSuccess) return PDHCG_E_MEM;
+  }
+  for (int i = 0; i < count; ++i)
+    HIPCHK(device_outputs(B->desc[i].P, B->desc[i].perm, B->io, B->d_outx + B->offx[i], B->d_outy + B->offy[i],
+                          dev, B->d_s ? B->d_s + B->offx[i] : nullptr, &res[i], st));
+  std::vector<double> ox, oy;
+  if (!dev) {
+    ox.resize(std::max<long>(B->offx[count], 1));
+    oy.resize(std::max<long>(B->offy[count], 1));
+    HIPCHK(hipMemcpyAsync(ox.data(), B->d_outx, sizeof(double) * B->offx[count], hipMemcpyDeviceToHost, st));
+    if (B->offy[count] > 0)
+      HIPCHK(hipMemcpyAsync(oy.data(), B->d_outy, sizeof(double) * B->offy[count], hipMemcpyDeviceToHost, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   double ks = 0.0;
   if (timing) {
@@ -1421,22 +1583,15 @@ int pdhcg_solve_batch(void* hv, const double* const* x0s, const double* const* y
   }
   if (dpt) {
     report_phases(dpt, B->grid);
-    (void)hipFree(dpt);
+    tbuf.release();
   }
-  std::vector<double> zx, zy;
   for (int i = 0; i < count; ++i) {
     const HostInstance& H = h->inst[i]->H;
     const Ctl& c = ctl[i];
     int status = c.status;
     if (status == 0) status = c.ktot >= h->s.max_iter ? PDHCG_MAX_ITER : PDHCG_TIME_LIMIT;
-    const double* wx = ox.data() + B->offx[i];
-    const double* wy = oy.data() + B->offy[i];
-    if (c.ktot == 0) {
-      zx.assign(std::max(H.n, 1), 0.0);
-      zy.assign(std::max(H.m, 1), 0.0);
-      wx = zx.data();
-      wy = zy.data();
-    }
+    const double* wx = dev ? nullptr : ox.data() + B->offx[i];
+    const double* wy = dev ? nullptr : oy.data() + B->offy[i];
     finish_result(H, c, status, wx, wy, B->desc[i].P.eta, h->setup_s, &res[i]);
     res[i].kernel_s = i == 0 ? ks : 0.0;
     res[i].kernel_launches = i == 0 ? 1 : 0;
@@ -1505,8 +1660,7 @@ int pdhcg_project_cones(int32_t type, int32_t dim, int64_t count, const double* 
   return e == hipSuccess ? PDHCG_OK : PDHCG_E_HIP;
 }
 
-int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {
-  Handle* h = (Handle*)hv;
+int pdhcg_get_trace(pdhcg_handle* h, int32_t inst, pdhcg_trace* t) {
   if (!h || !t || inst < 0 || inst >= (int)h->inst.size()) return PDHCG_E_ARG;
   Instance* I = h->inst[inst];
   const TraceBufs& T = h->B ? h->B->desc[inst].T : I->T;
@@ -1551,9 +1705,8 @@ int pdhcg_get_trace(void* hv, int32_t inst, pdhcg_trace* t) {
   return PDHCG_OK;
 }
 
-int pdhcg_get_scaling(void* hv, int32_t inst, double* Sx, double* Sy, double* nu_b, double* nu_c,
+int pdhcg_get_scaling(pdhcg_handle* h, int32_t inst, double* Sx, double* Sy, double* nu_b, double* nu_c,
                       double* eta, double* omega0) {
-  Handle* h = (Handle*)hv;
   if (!h || inst < 0 || inst >= (int)h->inst.size()) return PDHCG_E_ARG;
   const Instance* I = h->inst[inst];
   if (Sx)
@@ -1566,8 +1719,7 @@ int pdhcg_get_scaling(void* hv, int32_t inst, double* Sx, double* Sy, double* nu
   return PDHCG_OK;
 }
 
-void pdhcg_free(void* hv) {
-  Handle* h = (Handle*)hv;
+void pdhcg_free(pdhcg_handle* h) {
   if (!h) return;
   free_batch(h->B);
   for (Instance* I : h->inst) free_instance(I);

@@ -54,8 +54,11 @@ struct DevProblem {
   const double* rhi;
   const double* xlo;     // n scaled box bounds (nullable: no box block)
   const double* xhi;
-  int ext;               // row bounds, box or fixed-middle EXP blocks present: the
-                         // kernel variant compiled with them (others leave them out)
+  int ext;               // row bounds, box or fixed-middle EXP blocks present, or the
+                         // rescaled-cone mode: the kernel variant compiled with them
+                         // (others leave them out)
+  int resc;              // rescaled-cone mode: SOC/RSOC/EXP/POW block j is S_j K_j,
+                         // S_j = diag(Sx on the block)
   const double* c;       // n (scaled)
   const double* qd;      // n diag(Q^)
   const double* Sx;      // n
@@ -185,6 +188,7 @@ struct InstDesc {
   const double* y0;   // scaled dual warm start (nullable)
   int la, lr, lg;     // lanes per row of A^T / P and of A, SOC/RSOC group width
   int n_warm;         // root warm-start slots (2 x (wave + lane items))
+  const int* perm;    // caller index of each internal coordinate (nullable)
 };
 
 struct BatchArgs {

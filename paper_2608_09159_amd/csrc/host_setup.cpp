@@ -330,10 +330,19 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   // ---- rescaling -------------------------------------------------------------
   H.Sx.assign(n, 1.0);
   H.Sy.assign(m, 1.0);
-  std::vector<std::pair<int, int>> blocks;  // non-elementwise cone blocks
-  for (const auto& cb : H.cones)
-    if (cb.type != PDHCG_CONE_FREE && cb.type != PDHCG_CONE_NONNEG && cb.type != PDHCG_CONE_BOX)
-      blocks.emplace_back(cb.start, cb.dim);
+  // blocks sharing one factor: every non-elementwise block in the
+  // cone-preserving mode; only the EXP1 blocks in the rescaled-cone mode,
+  // where SOC/RSOC/EXP/POW coordinates keep their own factors
+  std::vector<std::pair<int, int>> blocks;
+  const bool resc = s.cone_scaling == PDHCG_SCALE_CONE;
+  for (const auto& cb : H.cones) {
+    if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG || cb.type == PDHCG_CONE_BOX) continue;
+    if (resc && cb.type != PDHCG_CONE_EXP1) {
+      H.resc = true;
+      continue;
+    }
+    blocks.emplace_back(cb.start, cb.dim);
+  }
   Csr& A = H.A;
   if (s.scaling) {
     std::vector<double> row(m), col(n);
@@ -450,7 +459,9 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   H.wave_start.clear(); H.wave_dim.clear(); H.wave_type.clear(); H.wave_euclid.clear();
   H.lane_start.clear(); H.lane_type.clear(); H.lane_euclid.clear(); H.lane_alpha.clear();
   for (const auto& cb : H.cones) {
-    bool euclid = true;
+    // the metric is constant on the block (the Euclidean formulas apply);
+    // never for a rescaled cone block, whose metric carries S_j^2
+    bool euclid = !(H.resc && cb.type != PDHCG_CONE_EXP1);
     for (int i = cb.start + 1; i < cb.start + cb.dim; ++i)
       if (H.qdiag[i] != H.qdiag[cb.start]) euclid = false;
     switch (cb.type) {

@@ -31,6 +31,7 @@ struct HostInstance {
   // bounds per coordinate (empty: no box block)
   std::vector<double> rlo, rhi, xlo, xhi;
   std::vector<double> Sx, Sy, qdiag;
+  bool resc = false;              // rescaled-cone mode with some SOC/RSOC/EXP/POW block
   double nu_b = 1, nu_c = 1;
   double norm_b = 0, norm_c = 0;  // of the original data
   bool q_diag = true;

@@ -649,6 +649,76 @@ __device__ Items cache_items(const DevProblem& P, Items I, Lds& L) {
   return I;
 }
 
+// rescaled-cone mode (eq. scaling-induced-metric): a block of the scaled
+// problem is S K with S = diag(Sx on the block), and
+//   Pi^M_{S K}(r) = S Pi^{S M S}_K(S^-1 r),
+// so a prox projection reads S^-1 r in the metric S M S (M = 1 when the
+// caller forces the Euclidean metric) and scales the root back by S; the
+// check's projection (kkt) reads the unscaled -s = -nu_c S s^ instead and
+// projects it onto K itself, in the Euclidean metric
+template <class Src>
+struct RescSrc {
+  Src s;
+  const double* sx;
+  double nu_c;
+  long st;
+  bool kkt, force;
+  __device__ double r(int j) const {
+    const double v = sx[st + j];
+    return kkt ? s.r(j) * (nu_c * v) : s.r(j) / v;
+  }
+  __device__ double m(int j) const {
+    const double v = sx[st + j];
+    return kkt ? 1.0 : (force ? 1.0 : s.m(j)) * (v * v);
+  }
+};
+
+template <class MakeSrc>
+__device__ __forceinline__ void project_items_resc(const DevProblem& P, const Items& I, bool force_euclid,
+                                                   MakeSrc make, double* dst, double* warm, long dbase, bool kkt) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gpw = 64 / I.lg;
+  const double* sx = P.Sx;
+  for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
+    const long st = wi_start(P, I, it);
+    const RescSrc<decltype(make(st))> src{make(st), sx, P.nu_c, st, kkt, force_euclid};
+    project_wave_item(wi_type(P, I, it), wi_dim(P, I, it), kkt, src,
+                      [dst, st, dbase, sx, kkt](int j, double v) { dst[st + j - dbase] = kkt ? v : v * sx[st + j]; },
+                      warm ? warm + it : nullptr, I.lg);
+  }
+  for (int kb = 0; I.l0 + kb < I.l1; kb += BLOCK) {
+    const int it = I.l0 + kb + wv + NWAVE * lane;
+    if (it >= I.l1) continue;
+    const long st = li_start(P, I, it);
+    const int ty = li_type(P, I, it);
+    Trip o;
+    if (ty == PDHCG_CONE_EXP1) {
+      // one common factor (kappa X), as in the cone-preserving mode
+      const auto raw = make(st);
+      const bool eu = force_euclid || li_euclid(P, I, it);
+      const double m0 = eu ? 1.0 : raw.m(0), m2 = eu ? 1.0 : raw.m(2);
+      o = kkt ? Trip{0.0, 0.0, 0.0} : project_exp1(raw.r(0), raw.r(2), m0, m2, P.Sx[st] / P.nu_b);
+    } else {
+      const RescSrc<decltype(make(st))> src{make(st), sx, P.nu_c, st, kkt, force_euclid};
+      const double r0 = src.r(0), r1 = src.r(1), r2 = src.r(2);
+      double m0 = 1.0, m1 = 1.0, m2 = 1.0;
+      if (!kkt) { m0 = src.m(0); m1 = src.m(1); m2 = src.m(2); }
+      double* w = warm ? warm + P.n_wave + it : nullptr;
+      o = ty == PDHCG_CONE_EXP ? project_exp(r0, r1, r2, m0, m1, m2, w)
+                               : project_pow(r0, r1, r2, li_alpha(P, I, it), m0, m1, m2, w);
+      if (!kkt) {
+        o.a *= sx[st];
+        o.b *= sx[st + 1];
+        o.c *= sx[st + 2];
+      }
+    }
+    dst[st - dbase] = o.a;
+    dst[st + 1 - dbase] = o.b;
+    dst[st + 2 - dbase] = o.c;
+  }
+  __syncthreads();
+}
+
 // warm (nullable): previous roots of the root-finding projections, one per
 // item (wave items first, then lane items), read as starting points and
 // overwritten with the new roots
@@ -656,6 +726,12 @@ template <bool EXT = false, class MakeSrc>
 __device__ __forceinline__ void project_items(const DevProblem& P, const Items& I, bool force_euclid, MakeSrc make,
                               double* dst, double* warm, unsigned long long* ptw = nullptr, long dbase = 0,
                               bool kkt = false) {
+  if constexpr (EXT) {
+    if (P.resc) {
+      project_items_resc(P, I, force_euclid, make, dst, warm, dbase, kkt);
+      return;
+    }
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gpw = 64 / I.lg;                       // groups per wave
   for (int it = I.w0 + wv * gpw + lane / I.lg; it < I.w1; it += NWAVE * gpw) {
@@ -924,7 +1000,9 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
                     V.warm + (P.n_wave + P.n_lane), nullptr, 0, true);
       for_item_coords(P, IT, [&](long i, bool act) {
         if (act) {
-          const double f = P.nu_c * P.Sx[i] * V.zb[i];
+          // Pi_K(-s) of the original problem: nu_c S_x Pi_K(-s^) when the
+          // block shares one factor; projected unscaled in the rescaled mode
+          const double f = (EXT && P.resc) ? V.zb[i] : P.nu_c * P.Sx[i] * V.zb[i];
           acc[1] += f * f;
         }
       });
@@ -1634,6 +1712,90 @@ __global__ __launch_bounds__(BLOCK) void fill_kernel(double* x, long n, double v
 }
 
 // ---------------------------------------------------------------------------
+// caller-facing vectors on the device: warm starts into the scaled space and
+// results out of it (Section "Problem Rescaling": x^ = S_x x / nu_b,
+// y^ = y / (nu_c S_y)), in the caller's coordinate order (perm[j] = the
+// caller's index of internal coordinate j; null: the same order)
+// ---------------------------------------------------------------------------
+// dst[j] = S[j] src[perm[j]] / nu (x in), or src[j] / (nu S[j]) (y in)
+__global__ __launch_bounds__(BLOCK) void scale_in_kernel(const double* src, const int* perm, const double* S,
+                                                         double nu, int inv, double* dst, long n) {
+  for (long j = (long)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (long)gridDim.x * BLOCK) {
+    const double v = src[perm ? perm[j] : j];
+    dst[j] = inv ? v / (nu * S[j]) : S[j] * v / nu;
+  }
+}
+
+// dst[perm[j]] = nu src[j] / S[j] (x out), or nu S[j] src[j] (y out)
+__global__ __launch_bounds__(BLOCK) void scale_out_kernel(const double* src, const int* perm, const double* S,
+                                                          double nu, int inv, double* dst, long n) {
+  for (long j = (long)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (long)gridDim.x * BLOCK)
+    dst[perm ? perm[j] : j] = inv ? nu * src[j] / S[j] : nu * S[j] * src[j];
+}
+
+// the factor part of Q^ w: per workgroup, partial sums of (R^ w)_k over a
+// slice of the coordinates (part[blockIdx.x * r + k])
+__global__ __launch_bounds__(BLOCK) void rdot_partial_kernel(const double* R, int r, long n, const double* w,
+                                                             double* part) {
+  __shared__ double red[NWAVE];
+  for (int k = 0; k < r; ++k) {
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK)
+      acc += R[(size_t)k * n + i] * w[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < NWAVE; ++q) t += red[q];
+      part[(size_t)blockIdx.x * r + k] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// ht = D^ (R^ w) from the partials of nb workgroups (one workgroup, fixed
+// summation order)
+__global__ __launch_bounds__(BLOCK) void rdot_finish_kernel(const double* part, int nb, int r, const double* D,
+                                                            double* ht) {
+  __shared__ double hh[RMAX];
+  if ((int)threadIdx.x < r) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[(size_t)b * r + threadIdx.x];
+    hh[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < r) {
+    double t = 0.0;
+    for (int j = 0; j < r; ++j) t += D[threadIdx.x * r + j] * hh[j];
+    ht[threadIdx.x] = t;
+  }
+}
+
+// the dual slack of the original problem at the unscaled (x, y) of the
+// scaled candidate (w, wy): s = nu_c S_x (Q^ w + c^ - A^T wy), with
+// Q^ w = diag(Q^) w (diagonal Q), or P^ w + R^T ht (ht = D^ R^ w)
+__global__ __launch_bounds__(BLOCK) void dual_slack_kernel(DevProblem P, const double* w, const double* wy,
+                                                           const double* ht, const int* perm, double* out) {
+  const long n = P.n;
+  for (long i = (long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+    double qw;
+    if (P.q_diag) {
+      qw = P.qd[i] * w[i];
+    } else {
+      qw = 0.0;
+      if (P.p_diag) qw = P.Pd[i] * w[i];
+      else if (P.P_ptr)
+        for (int64_t k = P.P_ptr[i]; k < P.P_ptr[i + 1]; ++k) qw += P.P_val[k] * w[P.P_col[k]];
+      for (int k = 0; k < P.r; ++k) qw += P.R[(size_t)k * n + i] * ht[k];
+    }
+    double aty = 0.0;
+    for (int64_t k = P.AT_ptr[i]; k < P.AT_ptr[i + 1]; ++k) aty += P.AT_val[k] * wy[P.AT_col[k]];
+    out[perm ? perm[i] : i] = P.nu_c * P.Sx[i] * (qw + P.c[i] - aty);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // batch kernels: independent instances, one workgroup per instance at a time
 // ---------------------------------------------------------------------------
 // before every batch launch: control blocks zeroed, scaled warm starts (or
@@ -1915,6 +2077,39 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t st) {
   int grid = (int)((n + BLOCK - 1) / BLOCK);
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(BLOCK), 0, st, x, n, v);
+  return hipGetLastError();
+}
+
+static int io_grid(long n) {
+  return (int)std::max<long>(1, std::min<long>((n + BLOCK - 1) / BLOCK, 2048));
+}
+
+hipError_t launch_scale_in(const double* src, const int* perm, const double* S, double nu, bool inv, double* dst,
+                           long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_in_kernel, dim3(io_grid(n)), dim3(BLOCK), 0, st, src, perm, S, nu, inv ? 1 : 0, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_out(const double* src, const int* perm, const double* S, double nu, bool inv, double* dst,
+                            long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_out_kernel, dim3(io_grid(n)), dim3(BLOCK), 0, st, src, perm, S, nu, inv ? 1 : 0, dst,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual_slack(const DevProblem& P, const double* w, const double* wy, const int* perm, double* io,
+                             double* out, hipStream_t st) {
+  if (P.n <= 0) return hipSuccess;
+  const double* ht = io;
+  if (!P.q_diag && P.r > 0) {
+    const int nb = std::min(IO_PARTS, io_grid(P.n));
+    double* part = io + RMAX;
+    hipLaunchKernelGGL(rdot_partial_kernel, dim3(nb), dim3(BLOCK), 0, st, P.R, P.r, (long)P.n, w, part);
+    hipLaunchKernelGGL(rdot_finish_kernel, dim3(1), dim3(BLOCK), 0, st, (const double*)part, nb, P.r, P.Dm, io);
+  }
+  hipLaunchKernelGGL(dual_slack_kernel, dim3(io_grid(P.n)), dim3(BLOCK), 0, st, P, w, wy, ht, perm, out);
   return hipGetLastError();
 }
 

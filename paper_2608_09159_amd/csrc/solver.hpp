@@ -18,6 +18,19 @@ hipError_t launch_norm(const double* x, long n, double* part, double* nrm, hipSt
 hipError_t launch_scale(double* x, long n, const double* nrm, hipStream_t st);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t st);
 
+// caller-facing vectors: warm starts in (x: S x / nu, inv: v / (nu S)) and
+// results out (x: nu v / S with inv, y: nu S v), through the caller order
+// perm (nullable); the dual slack s = nu_c S_x (Q^ w + c^ - A^T wy) of the
+// original problem into out[perm[i]]; io: IO_DOUBLES doubles of scratch
+constexpr int IO_PARTS = 64;
+constexpr int IO_DOUBLES = RMAX + IO_PARTS * RMAX;
+hipError_t launch_scale_in(const double* src, const int* perm, const double* S, double nu, bool inv, double* dst,
+                           long n, hipStream_t st);
+hipError_t launch_scale_out(const double* src, const int* perm, const double* S, double nu, bool inv, double* dst,
+                            long n, hipStream_t st);
+hipError_t launch_dual_slack(const DevProblem& P, const double* w, const double* wy, const int* perm, double* io,
+                             double* out, hipStream_t st);
+
 // diagnostics of failed cone root-finding
 hipError_t reset_cone_failure(hipStream_t st);
 hipError_t read_cone_failure(double rec[8], unsigned* count);

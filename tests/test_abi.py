@@ -101,6 +101,14 @@ def test_rejects_bad_settings(lib):
     assert _setup_rc(p, tol=0.0) == -1
     assert _setup_rc(p, rho=0.3) == -1
     assert _setup_rc(p, lanes_at=3) == -1
+    assert _setup_rc(p, cone_scaling=2) == -1
+    assert _setup_rc(p, memory_kind=2) == -1
+    # an allocator needs both callbacks
+    s = G.default_settings()
+    s.dev_alloc = G.TORCH_ALLOC
+    m = G._Marshalled(p)
+    h = C.c_void_p()
+    assert G.load().pdhcg_setup(C.byref(m.pc), 1, C.byref(s), C.byref(h)) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -129,6 +137,8 @@ def test_batch_binding_needs_two_problems(lib):
 def test_defaults_of_execution_settings(lib):
     s = G.default_settings()
     assert s.autotune == 1 and s.tune_iters == 64 and s.time_kernels == 0
+    assert s.cone_scaling == 0 and s.interleave == 0       # cone-preserving block scaling
+    assert s.memory_kind == 0 and not s.dev_alloc and not s.dev_free and not s.alloc_ctx
 
 
 def test_setup_rejects_invalid_bounds():
