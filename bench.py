@@ -49,7 +49,13 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # workload, grid, iterations per launch, the kernel sources' sha256 and
 # bytes_per_launch.  Valid only for the recorded kernel sources, grid and
 # iteration count; otherwise (and while None) the bench reports null.
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {
+    "workload": "large_sparse_qp", "grid": 256, "iterations": 256,
+    "sources_sha256": "5ac7da9f593e6b13da209999b34624c88e97c79e816735b3cf40c9c7716e17d9",
+    # FETCH_SIZE 3,559,528,130.4 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 476,975,840.2 KiB x 1.0, per 256-iteration launch
+    "bytes_per_launch": 7777377593669.3,
+}
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
 
