@@ -51,10 +51,10 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "large_sparse_qp", "grid": 256, "iterations": 256,
-    "sources_sha256": "5ac7da9f593e6b13da209999b34624c88e97c79e816735b3cf40c9c7716e17d9",
-    # FETCH_SIZE 3,559,528,130.4 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 476,975,840.2 KiB x 1.0, per 256-iteration launch
-    "bytes_per_launch": 7777377593669.3,
+    "sources_sha256": "112f22e7872de72946c8304302124a8dc2783f0b5eedaffcd2b14ef8d391e80f",
+    # FETCH_SIZE 3,571,938,632.5 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 477,662,023.4 KiB x 1.0, per 256-iteration launch
+    "bytes_per_launch": 7803507558139.4,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 

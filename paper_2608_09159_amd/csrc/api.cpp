@@ -453,10 +453,16 @@ int upload_instance(Handle* h, Instance* I) {
     cu.reserve(n);
     cheavy.reserve(n);
     ckind.reserve(n);
-    // a coordinate whose A^T or P row has at least 4096 nonzeros and more
-    // than 5% of a workgroup's share of all of them
-    const double rownz_total = (double)H.AT.nnz() + (double)(H.P.rows > 0 ? H.P.nnz() : 0);
-    const double heavy_nz = std::max(4096.0, 0.05 * rownz_total / G);
+    // heavy: a unit with an A^T or P row of at least 4096 nonzeros and over
+    // half a workgroup's share of the total weight (flags set below, once
+    // the total is known).  Lighter long rows share a workgroup with other
+    // coordinates and run in the A^T length classes; a dedicated workgroup
+    // holds one coordinate's P and elementwise work, so below that size it
+    // idles through the inner loop (measured on the large sparse QP: 60 of
+    // 256 workgroups dedicated at 5% of a share waited at the grid barriers
+    // for a third of the solve)
+    std::vector<double> unit_nz;
+    unit_nz.reserve(n);
     auto rownz = [&](long i) {
       double z = (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
       if (H.P.rows > 0) z = std::max(z, (double)(H.P.ptr[i + 1] - H.P.ptr[i]));
@@ -465,17 +471,25 @@ int upload_instance(Handle* h, Instance* I) {
     for (const auto& cb : H.cones) {
       // per-coordinate work of one outer iteration: the A^T row once, the
       // elementwise work, P row (unless P is diagonal) and factor columns
-      // once per prox step (about fq of them for a general Q)
+      // once per prox step (about fq of them for a general Q).  With a
+      // sparse P the inner loop's P products dominate and run in phases of
+      // their own, so the A^T row, read in the one phase per iteration that
+      // precedes them, counts 1/fq of its nonzeros: ownership leans towards
+      // the inner loop's work (measured on the large sparse QP, whose
+      // power-law A^T rows otherwise give the slack columns' workgroups 28%
+      // more P rows in every inner step)
       const double fq = H.q_diag ? 1.0 : 3.0;
+      const bool sparse_p = H.P.rows > 0 && !H.p_diag;
+      const double at_w = sparse_p ? 1.0 / fq : 1.0;
       auto wcoord = [&](long i) {
-        double w = fq * (2.0 + H.r) + (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
-        if (H.P.rows > 0 && !H.p_diag) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
+        double w = fq * (2.0 + H.r) + at_w * (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+        if (sparse_p) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
         return w;
       };
       if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG || cb.type == PDHCG_CONE_BOX) {
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
           cu.emplace_back(i + 1, wcoord(i));
-          cheavy.push_back(rownz(i) > heavy_nz);
+          unit_nz.push_back(rownz(i));
           ckind.push_back(0);
         }
       } else {
@@ -487,9 +501,15 @@ int upload_instance(Handle* h, Instance* I) {
         if (cb.type == PDHCG_CONE_EXP) w += 180.0 * fq;
         if (cb.type == PDHCG_CONE_POW) w += 320.0 * fq;
         cu.emplace_back((long)cb.start + cb.dim, w);
-        cheavy.push_back(zmax > heavy_nz);
+        unit_nz.push_back(zmax);
         ckind.push_back((signed char)(1 + cb.type));
       }
+    }
+    {
+      double wtot = 0.0;
+      for (const auto& u : cu) wtot += u.second;
+      const double heavy_nz = std::max(4096.0, 0.5 * wtot / G);
+      for (double z : unit_nz) cheavy.push_back(z > heavy_nz);
     }
     // with many alternating kinds the kind boundaries would fragment the
     // split: keep them only while there are few kind runs
@@ -541,8 +561,11 @@ int upload_instance(Handle* h, Instance* I) {
       long nr = pc[w + 1] - pc[w];
       double nz = 0.0, zmax = 0.0;
       if (nr > 0) {
+        // with A^T in length classes the workgroup's lanes serve its P rows
+        // (and the setup products) only
+        const double pnz = H.P.rows > 0 ? (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]) : 0.0;
         nz = (double)(H.AT.ptr[pc[w + 1]] - H.AT.ptr[pc[w]]);
-        if (H.P.rows > 0) nz = std::max(nz, (double)(H.P.ptr[pc[w + 1]] - H.P.ptr[pc[w]]));
+        if (H.P.rows > 0) nz = at_classes ? pnz : std::max(nz, pnz);
         for (long i = pc[w]; i < pc[w + 1]; ++i) {
           double z = H.P.rows > 0 ? (double)(H.P.ptr[i + 1] - H.P.ptr[i]) : 0.0;
           if (!at_classes) z = std::max(z, (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]));
