@@ -110,6 +110,31 @@ def test_iterate_parity_row_classes(tmp_path):
     trace_parity(p, grid_dim=24, iters=30)
 
 
+def test_partition_long_rows_share_workgroups(tmp_path):
+    """Large sparse QP family at n = 1e6 (power-law A^T rows, sparse P): a
+    workgroup of its own only for a row above half a workgroup's share of the
+    coordinate weight (fq (2 + r) + nnz(A^T row) / fq + fq nnz(P row), fq = 3),
+    so every other workgroup holds P rows, within 1.4x of the mean.  (The
+    same instance's iterates are compared with the oracle in
+    test_gpu_parity_full.test_large_sparse_qp_1e6_first_iterations.)"""
+    p = synth.large_sparse_qp(seed=2, n=1_000_000, m=500_000)
+    part = _partition_dump(p, tmp_path)
+    atn = np.diff(p.A.tocsc().indptr).astype(float)
+    pn = np.diff(p.P.tocsr().indptr).astype(float)
+    G = len(part)
+    w = 3.0 * 2.0 + atn / 3.0 + 3.0 * pn
+    heavy = max(4096.0, 0.5 * w.sum() / G)
+    pw = []
+    for _, c0, c1 in part[:, [0, 1, 2]]:
+        if c1 - c0 == 1:
+            assert max(atn[c0], pn[c0]) > heavy, (c0, atn[c0], heavy)
+        pw.append(pn[c0:c1].sum())
+    pw = np.array(pw)
+    print(f"[partition] G={G} dedicated={(part[:, 2] - part[:, 1] == 1).sum()} "
+          f"P nnz per workgroup max/mean {pw.max() / pw.mean():.3f}", flush=True)
+    assert pw.max() <= 1.4 * pw.mean()
+
+
 def test_iterate_parity_edge_cones():
     trace_parity(edge_cone_problem())
     trace_parity(edge_cone_problem(1), grid_dim=3)
