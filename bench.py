@@ -50,11 +50,11 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # bytes_per_launch.  Valid only for the recorded kernel sources, grid and
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
-    "workload": "large_sparse_qp", "grid": 256, "iterations": 256,
-    "sources_sha256": "112f22e7872de72946c8304302124a8dc2783f0b5eedaffcd2b14ef8d391e80f",
-    # FETCH_SIZE 3,571,938,632.5 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 477,662,023.4 KiB x 1.0, per 256-iteration launch
-    "bytes_per_launch": 7803507558139.4,
+    "workload": "large_sparse_qp", "grid": 512, "iterations": 256,
+    "sources_sha256": "162054d2508303243129d73c2ef6d335ff1c7c4c8f2a7a59cb192d1e58520051",
+    # FETCH_SIZE 4,167,707,657.1 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 478,915,765.7 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
+    "bytes_per_launch": 9024784397991.5,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
@@ -447,6 +447,21 @@ def timed_solves(prob, args, budget, precision="fp64", verbose=0):
     return runs, wall, setup_s
 
 
+def solver_kernel_name(prob, precision, grid):
+    """The library's solver kernel for this solve: FP32 bulk, one workgroup,
+    the implementation-form features (row bounds, boxes, fixed-middle EXP),
+    or, without cone blocks, the cone-free kernel at two workgroups per CU."""
+    kinds = {k for k, _, _, _ in prob.cones}
+    ext = getattr(prob, "row_lo", None) is not None or bool(kinds & {"box", "exp1"})
+    if precision == "fp32":
+        return "solve_kernel_f32_ext" if ext else "solve_kernel_f32"
+    if grid == 1:
+        return "solve_kernel_one_ext" if ext else "solve_kernel_one"
+    if ext:
+        return "solve_kernel_ext"
+    return "solve_kernel" if kinds & {"soc", "rsoc", "exp", "pow"} else "solve_kernel_lin"
+
+
 def rel_kkt(r):
     return max(r["rel_primal"], r["rel_dual"], r["rel_gap"])
 
@@ -694,7 +709,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
-                     "kernel": "solve_kernel", "kernel_avg_launch_ms": 1e3 * ksum / launches,
+                     "kernel": solver_kernel_name(prob, "fp64", grid), "kernel_avg_launch_ms": 1e3 * ksum / launches,
                      "launch": [grid, runs[-1]["block_dim"]],
                      "algorithmic_bytes_per_iteration": alg_bytes / iters,
                      "bytes_model": "method (A, A^T, P read once per product, ideal gathers)"},

@@ -332,9 +332,12 @@ int upload_instance(Handle* h, Instance* I) {
   }
   if (B.err != hipSuccess) return B.err == hipErrorOutOfMemory ? PDHCG_E_MEM : PDHCG_E_HIP;
 
-  // launch geometry
+  // launch geometry: at most the workgroups resident at once for the kernel
+  // this solve runs (two per CU for problems without cone blocks)
+  const bool fp32 = h->s.precision == PDHCG_PREC_FP32;
+  const bool has_cones = !H.wave_start.empty() || !H.lane_start.empty();
   int maxg = 1;
-  HIPCHK(max_resident_grid(&maxg));
+  HIPCHK(max_resident_grid_for(fp32, P.ext != 0, has_cones, 0, &maxg));
   int G = h->s.grid_dim;
   if (G <= 0) {
     long work = std::max<long>(std::max<long>(n, m), 1);
@@ -588,6 +591,12 @@ int upload_instance(Handle* h, Instance* I) {
     for (int w = 0; w < G; ++w) maxloc = std::max(maxloc, pc[w + 1] - pc[w]);
     const size_t rbytes = (size_t)H.r * (size_t)maxloc * sizeof(double);
     I->lds_bytes = (H.r > 0 && rbytes <= (size_t)64 * 1024) ? (int)rbytes : 0;
+    if (I->lds_bytes > 0) {
+      // the slice must not cost the grid its residency
+      int mg = 0;
+      HIPCHK(max_resident_grid_for(fp32, P.ext != 0, has_cones, I->lds_bytes, &mg));
+      if (mg < G) I->lds_bytes = 0;
+    }
     // skewed A^T row lengths (some row of a workgroup more than 16 times its
     // mean and longer than 64): order each workgroup's rows by length class
     // (<= 16, 64, 256, 1024 nonzeros, longer), run with 1, 4, 16, 64 and 512

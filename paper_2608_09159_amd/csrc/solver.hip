@@ -1584,7 +1584,7 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
 // ---------------------------------------------------------------------------
 // single-problem kernel: the whole grid is one team
 // ---------------------------------------------------------------------------
-template <class MV, bool SOLO, bool EXT>
+template <class MV, bool SOLO, bool EXT, bool CONES = true>
 __device__ void solve_body(const KArgs& A) {
   __shared__ Lds L;
   const int rank = blockIdx.x, G = gridDim.x;
@@ -1613,10 +1613,10 @@ __device__ void solve_body(const KArgs& A) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   const Run run{&A.S, &A.T, A.stop_at, A.qmax, 0ull, A.lds_bytes > 0 ? dyn_lds : nullptr, A.lds_bytes};
   if constexpr (SOLO) {
-    run_solver<true, MV, EXT>(run, P, A.V, A.ctl, SoloTeam{}, L, own, prof);
+    run_solver<CONES, MV, EXT>(run, P, A.V, A.ctl, SoloTeam{}, L, own, prof);
   } else {
     GridTeam T{A.bar, A.spin_limit, rank, G};
-    run_solver<true, MV, EXT>(run, P, A.V, A.ctl, T, L, own, prof);
+    run_solver<CONES, MV, EXT>(run, P, A.V, A.ctl, T, L, own, prof);
   }
   tmark(L, prof, PT_INIT);
   __syncthreads();
@@ -1628,6 +1628,11 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel(KArgs A) { solve_body<doub
 
 // row bounds, boxes and fixed-middle EXP blocks
 __global__ __launch_bounds__(BLOCK) void solve_kernel_ext(KArgs A) { solve_body<double, false, true>(A); }
+
+// problems without cone blocks (FREE / R+ only, no EXT feature): compiled
+// without the projection code, at 4 waves per SIMD (two workgroups per CU),
+// so twice the gathers of the latency-bound products are in flight
+__global__ __launch_bounds__(BLOCK, 4) void solve_kernel_lin(KArgs A) { solve_body<double, false, false, false>(A); }
 
 // FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
 __global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false, false>(A); }
@@ -1987,13 +1992,21 @@ int block_size() { return BLOCK; }
 // with this kernel's registers and LDS (the barrier's waits are bounded as
 // well, so a grid that cannot all be resident ends with PDHCG_ABORTED, not a
 // hang).
+// the solver kernel of a launch: FP32 bulk or FP64, a grid of one
+// workgroup, the EXT features, problems without cone blocks
+static const void* solver_kernel_for(bool fp32, bool ext, bool cones, int grid) {
+  if (fp32) return ext ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32;
+  if (grid == 1) return ext ? (const void*)solve_kernel_one_ext : (const void*)solve_kernel_one;
+  if (ext) return (const void*)solve_kernel_ext;
+  return cones ? (const void*)solve_kernel : (const void*)solve_kernel_lin;
+}
+
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream) {
   KArgs a = args;
   void* params[] = {&a};
   const bool ext = args.P.ext != 0;
-  const void* k = fp32 ? (ext ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32)
-                       : (grid == 1 ? (ext ? (const void*)solve_kernel_one_ext : (const void*)solve_kernel_one)
-                                    : (ext ? (const void*)solve_kernel_ext : (const void*)solve_kernel));
+  const bool cones = args.P.n_wave > 0 || args.P.n_lane > 0;
+  const void* k = solver_kernel_for(fp32, ext, cones, grid);
   int dev = 0, ncu = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -2003,23 +2016,24 @@ hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stre
   return hipLaunchKernel(k, dim3(grid), dim3(BLOCK), params, (size_t)args.lds_bytes, stream);
 }
 
-hipError_t max_resident_grid(int* out) {
-  int dev = 0, ncu = 0, per = 0;
+hipError_t max_resident_grid_for(bool fp32, bool ext, bool cones, int lds_bytes, int* out) {
+  int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  // FP32 mode polishes in FP64 on the same grid: both kernels must fit
+  int per = 0, per64 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per64, solver_kernel_for(false, ext, cones, 2), BLOCK,
+                                                   (size_t)lds_bytes);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)solve_kernel, BLOCK, 0);
-  if (e != hipSuccess) return e;
-  int per32 = 0, perx = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)solve_kernel_f32, BLOCK, 0);
-  if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&perx, (const void*)solve_kernel_ext, BLOCK, 0);
-  if (e != hipSuccess) return e;
-  per = std::min(per, perx);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&perx, (const void*)solve_kernel_f32_ext, BLOCK, 0);
-  if (e != hipSuccess) return e;
-  *out = std::min(per, std::min(per32, perx)) * ncu;
+  per = per64;
+  if (fp32) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, solver_kernel_for(true, ext, cones, 2), BLOCK,
+                                                     (size_t)lds_bytes);
+    if (e != hipSuccess) return e;
+    per = std::min(per, per64);
+  }
+  *out = per * ncu;
   return hipSuccess;
 }
 

@@ -8,7 +8,8 @@ namespace pdhcg {
 
 int block_size();
 hipError_t launch_solve(const KArgs& args, bool fp32, int grid, hipStream_t stream);
-hipError_t max_resident_grid(int* out);
+// workgroups resident at once for the kernel(s) a solve of this kind runs
+hipError_t max_resident_grid_for(bool fp32, bool ext, bool cones, int lds_bytes, int* out);
 hipError_t launch_spmv(const int64_t* ptr, const int* col, const double* val, const double* x,
                        double* y, long rows, int Lw, hipStream_t st);
 // rows of perm in five length classes (seg[0..5]: class boundaries in perm)
