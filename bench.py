@@ -51,10 +51,10 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "large_sparse_qp", "grid": 512, "iterations": 256,
-    "sources_sha256": "162054d2508303243129d73c2ef6d335ff1c7c4c8f2a7a59cb192d1e58520051",
-    # FETCH_SIZE 4,167,707,657.1 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 478,915,765.7 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
-    "bytes_per_launch": 9024784397991.5,
+    "sources_sha256": "19333f19bb3f7a294a4f7ee8d60ef4994d0f9285b6f5b15ce525c54e0975031e",
+    # FETCH_SIZE 3,722,743,583.8 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 480,685,726.3 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
+    "bytes_per_launch": 8115394145195.7,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 

@@ -1373,18 +1373,17 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
     } else {
     {
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
+      if (check) {
         // check iterations use the FP64 data: the residuals and the restart
         // statistics of a check are exact FP64
-        const double aw = check ? spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, Lr, act)
-                                : spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
-        if (act && sub == 0) {
-          const double yl = V.y[l], axl = V.Ax[l];
-          const double wy = dual_cand<EXT>(P, l, yl, 2.0 * aw - axl, sigma);
-          V.wy[l] = wy;
-          V.Aw[l] = aw;
-          if (tracing) TB.wy[L.C.ktot * m + l] = wy;
-          if (check) {
+        for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
+          const double aw = spmv_row(P.A_ptr, P.A_col, P.A_val, W, l, sub, Lr, act);
+          if (act && sub == 0) {
+            const double yl = V.y[l], axl = V.Ax[l];
+            const double wy = dual_cand<EXT>(P, l, yl, 2.0 * aw - axl, sigma);
+            V.wy[l] = wy;
+            V.Aw[l] = aw;
+            if (tracing) TB.wy[L.C.ktot * m + l] = wy;
             const double dy = yl - wy;
             acc[0] += dy * dy;                           // SL_DY2
             acc[1] += (axl - aw) * dy;                   // SL_ADXDY
@@ -1393,12 +1392,23 @@ __device__ void run_solver(const Run& A, const DevProblem& P, const DevVec& V, C
             acc[3] += row_dual_term<EXT>(P, l, wy);           // SL_BY
             const double my = wy - V.ay[l];
             acc[4] += my * my;                           // SL_MOVY2
-          } else {
+          }
+        });
+      } else {
+        // the reflected-Halpern update of y and A x fused into the pass
+        for_rows_range(r0, r1, Lr, [&](long l, int sub, bool act) {
+          const double aw = spmv_row(P.A_ptr, P.A_col, M.A, W, l, sub, Lr, act);
+          if (act && sub == 0) {
+            const double yl = V.y[l], axl = V.Ax[l];
+            const double wy = dual_cand<EXT>(P, l, yl, 2.0 * aw - axl, sigma);
+            V.wy[l] = wy;
+            V.Aw[l] = aw;
+            if (tracing) TB.wy[L.C.ktot * m + l] = wy;
             V.y[l] = c1h * (2.0 * rho * wy + (1.0 - 2.0 * rho) * yl) + c3h * V.ay[l];
             V.Ax[l] = c1h * (2.0 * rho * aw + (1.0 - 2.0 * rho) * axl) + c3h * V.Aa[l];
           }
-        }
-      });
+        });
+      }
       if constexpr (SOLO) {
         if (!check) hw_clear(L);
       }
