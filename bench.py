@@ -335,10 +335,11 @@ def bench_warm(args):
     fam = W.FisherFamily()
     ntr = args.train_instances
     model, info = W.build_and_train(fam, list(range(1, ntr + 1)), tol=args.tol, epochs=args.epochs,
-                                    lr=args.lr)
+                                    lr=args.lr, log=log)
+    log(f"trained: loss {info['loss'][0]:.4f} -> {info['loss'][-1]:.4f}")
     try:
         ev = W.evaluate(model, fam, list(range(1_000_001, 1_000_001 + args.eval_instances)), tol=args.tol,
-                        timed=args.timed)
+                        timed=args.timed, log=log)
     finally:
         model.free()
     out = {

@@ -308,7 +308,7 @@ def fisher_paper(n_buyers=1_000, seed=1, middle="fixed"):
 
 
 def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
-           dist="lognormal", graph=None, middle="row"):
+           dist="lognormal", graph=None, middle="row", spread=None, base_seed=0):
     """Fisher market in the exponential-cone form of eq. fisher-conic with the
     middle exponential-cone coordinate held at one by an explicit row.
 
@@ -320,6 +320,11 @@ def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
     dist="lognormal": u_ij ~ lognormal(0,1), w_i ~ lognormal(0,0.5), b_j = 1.
     dist="paper":     u_ij, w_i ~ U[0.1, 1.1], b_j = 0.2 n (the paper's
                       Fisher experiment recipe).
+    spread (lognormal only): the instance is a perturbation of the base
+                      market drawn from `base_seed`, u = u0 exp(spread g),
+                      w = w0 exp(spread g') with g, g' ~ N(0,1) from `seed`
+                      (a family whose solution moves smoothly with its
+                      parameters).
     middle="row":     (z_i, s_i, t_i) in an exponential-cone block and a row
                       s_i = 1 (m + 2n rows);
     middle="fixed":   the block (z_i, 1, t_i) with its middle coordinate fixed
@@ -330,7 +335,12 @@ def fisher(seed=1, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0,
     bi, gj = graph
     e = bi.size
     rng = np.random.default_rng(seed)
-    if dist == "lognormal":
+    if dist == "lognormal" and spread is not None:
+        base = np.random.default_rng(base_seed)
+        u = base.lognormal(0.0, 1.0, size=e) * np.exp(spread * rng.standard_normal(e))
+        w = base.lognormal(0.0, 0.5, size=n_buyers) * np.exp(spread * rng.standard_normal(n_buyers))
+        supply = np.ones(n_goods)
+    elif dist == "lognormal":
         u = rng.lognormal(0.0, 1.0, size=e)
         w = rng.lognormal(0.0, 0.5, size=n_buyers)
         supply = np.ones(n_goods)

@@ -43,28 +43,34 @@ class Standardizer:
 
 
 class FisherFamily:
-    """Fisher markets on one valuation graph (instances.synth.fisher)."""
+    """Fisher markets on one valuation graph (instances.synth.fisher).
+    spread=None: independent lognormal valuations and budgets per instance;
+    spread=s: lognormal perturbations of one base market (smooth solution
+    map)."""
 
-    def __init__(self, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0):
+    def __init__(self, n_buyers=1000, n_goods=500, density=0.1, graph_seed=0, spread=None):
         from instances import synth
         self._synth = synth
-        self.n_buyers, self.n_goods, self.density = n_buyers, n_goods, density
+        self.n_buyers, self.n_goods, self.density, self.spread = n_buyers, n_goods, density, spread
         self.graph = synth.fisher_graph(n_buyers, n_goods, density, graph_seed)
 
     def instance(self, seed):
         return self._synth.fisher(seed=seed, n_buyers=self.n_buyers, n_goods=self.n_goods,
-                                  density=self.density, graph=self.graph)
+                                  density=self.density, graph=self.graph, spread=self.spread)
 
     @staticmethod
     def features(prob):
         return np.concatenate([np.log(prob.meta["u"]), np.log(prob.meta["w"])])
 
 
-def solve_family(probs, chunk=256, x0s=None, y0s=None, **settings):
+def solve_family(probs, chunk=256, x0s=None, y0s=None, log=None, **settings):
     """Batched solves of `probs` (pdhcg_solve_batch, `chunk` instances per
-    launch); returns the list of result dicts."""
+    launch); returns the list of result dicts.  log(msg), when given, hears
+    of every launch."""
     out = []
     for s in range(0, len(probs), chunk):
+        if log and s > 0:
+            log(f"solved {s} of {len(probs)}")
         part = probs[s:s + chunk]
         xs = None if x0s is None else x0s[s:s + chunk]
         ys = None if y0s is None else y0s[s:s + chunk]
@@ -148,7 +154,7 @@ def build_and_train(family, train_seeds, tol=1e-6, epochs=30, batch=256, lr=1e-3
     the network.  Returns (model, info)."""
     t0 = time.perf_counter()
     probs = [family.instance(s) for s in train_seeds]
-    res = solve_family(probs, tol=tol)
+    res = solve_family(probs, tol=tol, log=log)
     t_label = time.perf_counter() - t0
     F = np.stack([family.features(p) for p in probs])
     T = np.stack([np.concatenate([r["x"], r["y"]]) for r in res])
@@ -166,15 +172,15 @@ def build_and_train(family, train_seeds, tol=1e-6, epochs=30, batch=256, lr=1e-3
     return model, info
 
 
-def evaluate(model, family, seeds, tol=1e-6, timed=None):
+def evaluate(model, family, seeds, tol=1e-6, timed=None, log=None):
     """Cold and warm solves of the held-out `seeds`.  Iterations for all of
     them (batched solves); wall time, network inference included, for the
     first `timed` seeds with single solves."""
     probs = [family.instance(s) for s in seeds]
     F = np.stack([family.features(p) for p in probs])
     preds = model.predict(F)
-    cold = solve_family(probs, tol=tol)
-    warm = solve_family(probs, tol=tol, x0s=[p[0] for p in preds], y0s=[p[1] for p in preds])
+    cold = solve_family(probs, tol=tol, log=log)
+    warm = solve_family(probs, tol=tol, x0s=[p[0] for p in preds], y0s=[p[1] for p in preds], log=log)
     ic = np.array([r["iterations"] for r in cold], float)
     iw = np.array([r["iterations"] for r in warm], float)
     out = dict(instances=len(probs),

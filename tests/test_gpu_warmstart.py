@@ -5,8 +5,14 @@ its training set in seconds).
 What is asserted: the network trained by the library's kernels reduces its
 training loss, and every warm-started solve reaches the same tolerance and
 the same objective (to 1e-6) as the cold solve of the same instance, so the
-learned seed never changes the answer.  What it gains is reported, not
-asserted (parity unpinned: an empirical A/B on held-out seeds)."""
+learned seed never changes the answer.  On the family of independent draws
+what it gains is reported, not asserted (parity unpinned: an empirical A/B
+on held-out seeds; measured, it gains nothing there).  On a family of small
+perturbations of one market, whose solution moves smoothly with its
+parameters, the learned seed must save held-out iterations: the median over
+64 held-out seeds at most 0.9 of the cold median (measured 0.83: 1280
+against 1536 outer iterations; the solver and the training are
+deterministic)."""
 import numpy as np
 import pytest
 
@@ -34,5 +40,19 @@ def test_warm_start_pipeline_small_family():
         for c, w in zip(cold, warm):
             assert abs(c["primal_obj"] - w["primal_obj"]) <= 1e-5 * max(1.0, abs(c["primal_obj"]))
             assert max(w["rel_primal"], w["rel_dual"], w["rel_gap"]) <= 1e-6
+    finally:
+        model.free()
+
+
+def test_warm_start_gain_on_a_smooth_family():
+    fam = W.FisherFamily(n_buyers=100, n_goods=50, density=0.2, spread=0.1)
+    model, info = W.build_and_train(fam, list(range(1, 513)), epochs=60, lr=1e-3)
+    try:
+        assert info["label_statuses"] == {"OPTIMAL": 512}
+        assert info["loss"][-1] < 0.6 * info["loss"][0]
+        ev = W.evaluate(model, fam, list(range(1_000_001, 1_000_065)))
+        print("[warm smooth] loss", info["loss"][0], "->", info["loss"][-1], "eval:", ev, flush=True)
+        assert ev["statuses_cold"] == {"OPTIMAL": 64} and ev["statuses_warm"] == {"OPTIMAL": 64}
+        assert ev["warm_iterations_median"] <= 0.9 * ev["cold_iterations_median"]
     finally:
         model.free()
