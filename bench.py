@@ -51,10 +51,11 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "large_sparse_qp", "grid": 512, "iterations": 256,
-    "sources_sha256": "19333f19bb3f7a294a4f7ee8d60ef4994d0f9285b6f5b15ce525c54e0975031e",
-    # FETCH_SIZE 3,722,743,583.8 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 480,685,726.3 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
-    "bytes_per_launch": 8115394145195.7,
+    "sources_sha256": "82a30f370d17add5042c599d644e1d3abd503b8977a18184cdba6723ee69524b",
+    # FETCH_SIZE 3,563,523,972.5 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 478,548,812.9 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
+    # (degree coordinate order)
+    "bytes_per_launch": 7787188120928.6,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 

@@ -106,6 +106,11 @@ extern "C" {
                                  and are projected through
                                  eq. scaling-induced-metric; EXP1 blocks keep
                                  one common factor (their set is not a cone)*/
+#define PDHCG_ORDER_CALLER -1 /* device coordinate order (settings.interleave):
+                                 the caller's                                */
+#define PDHCG_ORDER_AUTO   0  /* DEGREE where it applies (see interleave)    */
+#define PDHCG_ORDER_CONES  1  /* cone blocks interleaved with FREE/R+        */
+#define PDHCG_ORDER_DEGREE 2  /* columns by nonzero count, dealt to ranges   */
 #define PDHCG_PREC_FP64   0
 #define PDHCG_PREC_FP32   1   /* FP32 copies of A, A^T, P, R for the bulk
                                  sweeps (A^T y, P u, R u, A w; FP32 products
@@ -213,12 +218,24 @@ typedef struct {
                                      phase; the FP64 polish then restarts at
                                      its candidate and runs to tol
                                      (<= 0: 10 * tol)                         */
-    int32_t interleave;           /* 1: on the device, interleave the cone
-                                     blocks with the FREE/R+ coordinates so
-                                     every workgroup gets a mix of both kinds
-                                     of work (inputs, outputs, traces and
-                                     scalings stay in the caller's order);
-                                     0 (default): the caller's order         */
+    int32_t interleave;           /* PDHCG_ORDER_*: the device's coordinate
+                                     order (inputs, outputs, traces and
+                                     scalings stay in the caller's order).
+                                     CONES: cone blocks interleaved with the
+                                     FREE/R+ coordinates, so every workgroup
+                                     gets a mix of both kinds of work.
+                                     DEGREE (cone-free problems): columns
+                                     sorted by their count of nonzeros in A,
+                                     the longest (at least 1/8 of a 1/512
+                                     share of A's and P's nonzeros, and
+                                     4096) first, the rest dealt in turn
+                                     to the ranges of 512 left beside the
+                                     head's workgroups.
+                                     AUTO (default): DEGREE for cone-free
+                                     problems with n >= 2^20 whose longest
+                                     column holds at least 64 times the mean
+                                     count, else the caller's order.
+                                     CALLER: the caller's order.             */
     int32_t cone_scaling;         /* PDHCG_SCALE_* (default BLOCK)            */
     int32_t memory_kind;          /* PDHCG_MEM_* of the caller's problem
                                      arrays, warm starts and outputs

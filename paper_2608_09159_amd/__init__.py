@@ -51,6 +51,7 @@ INNER = {"jacobi": 0, "euclid": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 CONE_SCALING = {"block": 0, "rescaled": 1}
 MEMORY_KIND = {"host": 0, "device": 1}
+ORDER = {"caller": -1, "auto": 0, "cones": 1, "degree": 2}   # settings.interleave
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -216,6 +217,8 @@ def default_settings(**kw) -> Settings:
             v = CONE_SCALING[v] if isinstance(v, str) else v
         elif k == "memory_kind":
             v = MEMORY_KIND[v] if isinstance(v, str) else v
+        elif k == "interleave":
+            v = ORDER[v] if isinstance(v, str) else v
         elif k == "allocator":
             if v == "torch":
                 s.dev_alloc, s.dev_free = TORCH_ALLOC, TORCH_FREE

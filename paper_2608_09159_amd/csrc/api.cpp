@@ -363,6 +363,8 @@ int upload_instance(Handle* h, Instance* I) {
     // segments between heavy units in proportion to their weight (at least
     // one per nonempty segment), and each segment is cut by cumulative
     // weight.  Without heavy units this is the plain cumulative split.
+    // units of kind kHeadKind: the head of a degree order (below)
+    const signed char kind_head = 100;
     auto split = [&](const std::vector<std::pair<long, double>>& units, const std::vector<char>& heavy_u,
                      const std::vector<signed char>& kind_u, long total_items, std::vector<long>& out) {
       struct Seg { size_t a, b; bool heavy; double w; int k; };
@@ -384,7 +386,35 @@ int upload_instance(Handle* h, Instance* I) {
       int nheavy = 0, nlight = 0;
       for (const auto& s : segs) (s.heavy ? nheavy : nlight) += 1;
       int avail = G - nheavy;
-      if ((nheavy == 0 && nlight <= 1) || avail < nlight) {
+      // head segments (kind_head) are packed in order: a new workgroup
+      // whenever the next unit would overflow the average light share, so a
+      // head workgroup holds at most that share or a single unit; their
+      // workgroup counts come from the packing, the other light segments
+      // share the rest
+      const double cap = avail > 0 ? wlight / avail : 0.0;
+      auto pack = [&](const Seg& sg, std::vector<long>* cuts) {
+        int bins = 1;
+        double cur = 0.0;
+        for (size_t u = sg.a; u < sg.b; ++u) {
+          if (cur > 0.0 && cur + units[u].second > cap) {
+            if (cuts) cuts->push_back(units[u - 1].first);
+            ++bins;
+            cur = 0.0;
+          }
+          cur += units[u].second;
+        }
+        return bins;
+      };
+      int khead = 0, nhead = 0;
+      double whead = 0.0;
+      for (auto& sg : segs)
+        if (!sg.heavy && kind_u[sg.a] == kind_head) {
+          sg.k = pack(sg, nullptr);
+          khead += sg.k;
+          whead += sg.w;
+          ++nhead;
+        }
+      if ((nheavy == 0 && nlight <= 1) || avail < nlight || avail - khead < nlight - nhead) {
         // plain cumulative split (also the fallback when there are too many
         // heavy units for dedicated workgroups)
         double total = 0.0;
@@ -401,24 +431,27 @@ int upload_instance(Handle* h, Instance* I) {
         return;
       }
       // proportional shares with at least one workgroup per light segment
+      const int avail_p = avail - khead;
+      const double wlight_p = wlight - whead;
+      auto is_head = [&](const Seg& sg) { return !sg.heavy && kind_u[sg.a] == kind_head; };
       int given = 0;
       for (auto& s : segs)
-        if (!s.heavy) {
-          s.k = std::max(1, (int)std::floor(avail * s.w / std::max(wlight, 1e-300)));
+        if (!s.heavy && !is_head(s)) {
+          s.k = std::max(1, (int)std::floor(avail_p * s.w / std::max(wlight_p, 1e-300)));
           given += s.k;
         }
-      while (given > avail) {          // take back from the largest shares
+      while (given > avail_p) {        // take back from the largest shares
         Seg* big = nullptr;
         for (auto& s : segs)
-          if (!s.heavy && s.k > 1 && (!big || s.w / s.k < big->w / big->k)) big = &s;
+          if (!s.heavy && !is_head(s) && s.k > 1 && (!big || s.w / s.k < big->w / big->k)) big = &s;
         if (!big) break;
         big->k -= 1;
         given -= 1;
       }
-      while (given < avail) {          // hand out the rest to the heaviest per workgroup
+      while (given < avail_p) {        // hand out the rest to the heaviest per workgroup
         Seg* big = nullptr;
         for (auto& s : segs)
-          if (!s.heavy && (!big || s.w / s.k > big->w / big->k)) big = &s;
+          if (!s.heavy && !is_head(s) && (!big || s.w / s.k > big->w / big->k)) big = &s;
         if (!big) break;
         big->k += 1;
         given += 1;
@@ -428,6 +461,13 @@ int upload_instance(Handle* h, Instance* I) {
       for (const auto& s : segs) {
         const long seg_end = units[s.b - 1].first;
         if (s.heavy || s.k == 1) {
+          out[++kk] = seg_end;
+          continue;
+        }
+        if (is_head(s)) {
+          std::vector<long> cuts;
+          pack(s, &cuts);
+          for (long c : cuts) out[++kk] = c;
           out[++kk] = seg_end;
           continue;
         }
@@ -473,29 +513,49 @@ int upload_instance(Handle* h, Instance* I) {
       if (H.P.rows > 0) z = std::max(z, (double)(H.P.ptr[i + 1] - H.P.ptr[i]));
       return z;
     };
+    // per-coordinate work of one outer iteration: the A^T row once, the
+    // elementwise work, P row (unless P is diagonal) and factor columns
+    // once per prox step (about fq of them for a general Q).  With a
+    // sparse P the inner loop's P products dominate and run in phases of
+    // their own, so the A^T row, read in the one phase per iteration that
+    // precedes them, counts 1/fq of its nonzeros: ownership leans towards
+    // the inner loop's work (measured on the large sparse QP, whose
+    // power-law A^T rows otherwise give the slack columns' workgroups 28%
+    // more P rows in every inner step)
+    const double fq = H.q_diag ? 1.0 : 3.0;
+    const bool sparse_p = H.P.rows > 0 && !H.p_diag;
+    const double at_w = sparse_p ? 1.0 / fq : 1.0;
+    auto wcoord = [&](long i) {
+      double w = fq * (2.0 + H.r) + at_w * (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
+      if (sparse_p) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
+      return w;
+    };
+    // the head of a degree order (its longest A^T rows) is a segment of its
+    // own, cut by the work of the A^T phase (A^T row and P row), in the
+    // units of the other coordinates' weight: each head workgroup gets an
+    // average workgroup's share of that phase, and no other workgroup
+    // carries a long A^T row beside a full share of P rows
+    double lam_head = 0.0;
+    if (H.head > 0 && sparse_p) {
+      double sw = 0.0, sz = 0.0;
+      for (long i = H.head; i < n; ++i) {
+        sw += wcoord(i);
+        sz += (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]) + (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
+      }
+      lam_head = sz > 0.0 ? sw / sz : 0.0;
+    }
+    auto whead = [&](long i) {
+      if (!sparse_p) return wcoord(i);
+      return lam_head * ((double)(H.AT.ptr[i + 1] - H.AT.ptr[i]) + (double)(H.P.ptr[i + 1] - H.P.ptr[i]));
+    };
+    const signed char kHeadKind = kind_head;
     for (const auto& cb : H.cones) {
-      // per-coordinate work of one outer iteration: the A^T row once, the
-      // elementwise work, P row (unless P is diagonal) and factor columns
-      // once per prox step (about fq of them for a general Q).  With a
-      // sparse P the inner loop's P products dominate and run in phases of
-      // their own, so the A^T row, read in the one phase per iteration that
-      // precedes them, counts 1/fq of its nonzeros: ownership leans towards
-      // the inner loop's work (measured on the large sparse QP, whose
-      // power-law A^T rows otherwise give the slack columns' workgroups 28%
-      // more P rows in every inner step)
-      const double fq = H.q_diag ? 1.0 : 3.0;
-      const bool sparse_p = H.P.rows > 0 && !H.p_diag;
-      const double at_w = sparse_p ? 1.0 / fq : 1.0;
-      auto wcoord = [&](long i) {
-        double w = fq * (2.0 + H.r) + at_w * (double)(H.AT.ptr[i + 1] - H.AT.ptr[i]);
-        if (sparse_p) w += fq * (double)(H.P.ptr[i + 1] - H.P.ptr[i]);
-        return w;
-      };
       if (cb.type == PDHCG_CONE_FREE || cb.type == PDHCG_CONE_NONNEG || cb.type == PDHCG_CONE_BOX) {
         for (long i = cb.start; i < cb.start + cb.dim; ++i) {
-          cu.emplace_back(i + 1, wcoord(i));
+          const bool hd = i < H.head;
+          cu.emplace_back(i + 1, hd ? whead(i) : wcoord(i));
           unit_nz.push_back(rownz(i));
-          ckind.push_back(0);
+          ckind.push_back(hd ? kHeadKind : 0);
         }
       } else {
         double w = 0.0, zmax = 0.0;
@@ -1238,7 +1298,7 @@ int pdhcg_default_settings(pdhcg_settings* s) {
   s->autotune = 1;
   s->tune_iters = 64;
   s->fp32_tol = 0.0;
-  s->interleave = 0;
+  s->interleave = PDHCG_ORDER_AUTO;
   s->cone_scaling = PDHCG_SCALE_BLOCK;
   return PDHCG_OK;
 }
@@ -1275,7 +1335,8 @@ int pdhcg_setup(const pdhcg_problem* probs, int32_t count, const pdhcg_settings*
       (s->scheme != PDHCG_SCHEME_RH && s->scheme != PDHCG_SCHEME_AVG) ||
       (s->scheme == PDHCG_SCHEME_AVG && (s->avg_epoch < 1 || s->precision != PDHCG_PREC_FP64)) ||
       (s->precision != PDHCG_PREC_FP64 && s->precision != PDHCG_PREC_FP32) || s->trace_iters < 0 ||
-      (s->cone_scaling != PDHCG_SCALE_BLOCK && s->cone_scaling != PDHCG_SCALE_CONE))
+      (s->cone_scaling != PDHCG_SCALE_BLOCK && s->cone_scaling != PDHCG_SCALE_CONE) ||
+      s->interleave < PDHCG_ORDER_CALLER || s->interleave > PDHCG_ORDER_DEGREE)
     return PDHCG_E_ARG;
   if (count > 1 && s->precision != PDHCG_PREC_FP64) return PDHCG_E_ARG;   // batches are FP64
   if ((s->memory_kind != PDHCG_MEM_HOST && s->memory_kind != PDHCG_MEM_DEVICE) ||

@@ -91,6 +91,8 @@ double norm2(const std::vector<double>& v) {
 // Renumbers everything indexed by coordinates (columns of A, rows and
 // columns of P, columns of R, c, S_x, the cone list) and records the
 // permutation; a no-op unless both kinds are present.
+void apply_coord_order(HostInstance& H, std::vector<int>& perm, std::vector<ConeBlock>& cones);
+
 void interleave(HostInstance& H) {
   H.perm.clear();
   const int n = H.n;
@@ -129,6 +131,15 @@ void interleave(HostInstance& H) {
     else
       cones.push_back(ConeBlock{u.type, ns, u.dim, u.alpha});
   }
+  apply_coord_order(H, perm, cones);
+}
+
+// Renumber everything indexed by coordinates (columns of A, rows and columns
+// of P, columns of R, c, S_x, box bounds) to the order perm (perm[j] = the
+// current index of new coordinate j), install the renumbered cone list and
+// record the permutation.
+void apply_coord_order(HostInstance& H, std::vector<int>& perm, std::vector<ConeBlock>& cones) {
+  const int n = H.n;
   std::vector<int> inv(n);
   for (int j = 0; j < n; ++j) inv[perm[j]] = j;
   // A: renumber columns, keep rows sorted by column
@@ -199,6 +210,71 @@ void interleave(HostInstance& H) {
   }
   H.cones.swap(cones);
   H.perm.swap(perm);
+}
+
+// Degree order of a problem whose coordinates are all elementwise (FREE,
+// R+ or box), for A^T rows of skewed length.  Coordinates are sorted by A^T
+// row length, longest first.  Rows of at least head_nz nonzeros stay in that
+// order at the front (H.head of them; the ownership partition packs that
+// head by the work of the A^T phase alone).  The rest are dealt to the
+// ranges left of `ranges` (one per workgroup of the partition, less the
+// head's) in turn, so that every range holds the same mix of row
+// lengths (with a sparse P the inner loop's P rows are then spread evenly
+// too) and neighbouring coordinates have similar lengths: a cache line of x
+// holds columns of similar degree, and the hot ones stay in L2 during the A
+// product.  Returns false (order unchanged) when some block is not
+// elementwise.
+bool degree_order(HostInstance& H, int ranges, double head_nz) {
+  const int n = H.n;
+  for (const auto& cb : H.cones)
+    if (cb.type != PDHCG_CONE_FREE && cb.type != PDHCG_CONE_NONNEG && cb.type != PDHCG_CONE_BOX) return false;
+  std::vector<int> type(n, PDHCG_CONE_FREE);
+  for (const auto& cb : H.cones)
+    for (int i = cb.start; i < cb.start + cb.dim; ++i) type[i] = cb.type;
+  std::vector<int64_t> deg(n, 0);
+  for (int64_t k = 0; k < H.A.nnz(); ++k) deg[H.A.col[k]]++;
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+  int head = 0;
+  while (head < n && (double)deg[ord[head]] >= head_nz) ++head;
+  std::vector<int> perm;
+  perm.reserve(n);
+  perm.insert(perm.end(), ord.begin(), ord.begin() + head);
+  // the partition packs the head into workgroups of about one range's share
+  // of the A^T phase (A^T row plus P row); the rest is dealt over the ranges
+  // left, so its ranges line up with the remaining workgroups
+  int head_bins = 0;
+  {
+    auto pnz = [&](int i) { return H.P.rows > 0 ? (double)(H.P.ptr[i + 1] - H.P.ptr[i]) : 0.0; };
+    const double share = (double)(H.A.nnz() + (H.P.rows > 0 ? H.P.nnz() : 0)) / std::max(ranges, 1);
+    double cur = 0.0;
+    for (int k = 0; k < head; ++k) {
+      const double z = (double)deg[ord[k]] + pnz(ord[k]);
+      if (cur > 0.0 && cur + z > share) {
+        ++head_bins;
+        cur = 0.0;
+      }
+      cur += z;
+    }
+    if (head > 0) ++head_bins;
+  }
+  const long rest = n - head;
+  const int R = (int)std::max<long>(1, std::min<long>(std::max(ranges - head_bins, 1), rest));
+  for (int r = 0; r < R; ++r)
+    for (long t = r; t < rest; t += R) perm.push_back(ord[head + t]);
+  // the cone list: runs of one elementwise type
+  std::vector<ConeBlock> cones;
+  for (int j = 0; j < n; ++j) {
+    const int ty = type[perm[j]];
+    if (!cones.empty() && cones.back().type == ty)
+      cones.back().dim += 1;
+    else
+      cones.push_back(ConeBlock{ty, j, 1, 0.0});
+  }
+  apply_coord_order(H, perm, cones);
+  H.head = head;
+  return true;
 }
 
 // divide entry (l, i) by row[l] * col[i]
@@ -427,7 +503,29 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   for (auto& v : H.D) v *= qs;
 
   // ---- device coordinate order ----------------------------------------------
-  if (s.interleave) interleave(H);
+  // Without cone blocks, skewed A^T rows (the longest at least 64 times the
+  // mean) on a large problem (n >= 2^20) get the degree order by default
+  // (interleave = 0); interleave = 2 forces it, -1 keeps the caller's order.
+  // It is dealt over 512 ranges, the solver's grid for such problems on a
+  // 256-CU device (two workgroups per CU); any grid size still gets an even
+  // mix.  The head takes the rows of at least 1/8 of a range's share of the
+  // A^T and P nonzeros (and at least 4096).
+  if (s.interleave == 1) {
+    interleave(H);
+  } else if (s.interleave == 0 || s.interleave == 2) {
+    bool want = s.interleave == 2;
+    if (!want && n >= (1 << 20) && A.nnz() > 0) {
+      std::vector<int64_t> deg(n, 0);
+      for (int64_t k = 0; k < A.nnz(); ++k) deg[A.col[k]]++;
+      const int64_t dmax = *std::max_element(deg.begin(), deg.end());
+      want = (double)dmax >= 64.0 * (double)A.nnz() / n;
+    }
+    if (want) {
+      const int ranges = 512;
+      const double share = (double)(A.nnz() + (hasP ? H.P.nnz() : 0)) / ranges;
+      degree_order(H, ranges, std::max(4096.0, share / 8.0));
+    }
+  }
 
   // ---- transpose, diagonal of Q^, structure flags -------------------------
   H.AT = transpose(A);

@@ -39,10 +39,13 @@ struct HostInstance {
   std::vector<double> pdiag;      // diag(P^) when p_diag
   std::vector<ConeBlock> cones;
   // device coordinate order: perm[j] = the caller's index of internal
-  // coordinate j (empty: the caller's order).  Cone blocks are interleaved
-  // with the elementwise coordinates so that contiguous ownership ranges
-  // mix both kinds of work.
+  // coordinate j (empty: the caller's order).  Either cone blocks are
+  // interleaved with the elementwise coordinates, so that contiguous
+  // ownership ranges mix both kinds of work, or the coordinates of a
+  // cone-free problem are in degree order (see build_instance).
   std::vector<int> perm;
+  // degree order: the first `head` coordinates hold the longest A^T rows
+  int head = 0;
   // per-coordinate kind and cone work items
   std::vector<uint8_t> ctype;
   std::vector<int> wave_start, wave_dim;

@@ -103,6 +103,8 @@ def test_rejects_bad_settings(lib):
     assert _setup_rc(p, lanes_at=3) == -1
     assert _setup_rc(p, cone_scaling=2) == -1
     assert _setup_rc(p, memory_kind=2) == -1
+    assert _setup_rc(p, interleave=3) == -1
+    assert _setup_rc(p, interleave=-2) == -1
     # an allocator needs both callbacks
     s = G.default_settings()
     s.dev_alloc = G.TORCH_ALLOC
@@ -137,7 +139,8 @@ def test_batch_binding_needs_two_problems(lib):
 def test_defaults_of_execution_settings(lib):
     s = G.default_settings()
     assert s.autotune == 1 and s.tune_iters == 64 and s.time_kernels == 0
-    assert s.cone_scaling == 0 and s.interleave == 0       # cone-preserving block scaling
+    assert s.cone_scaling == 0                             # cone-preserving block scaling
+    assert s.interleave == G.ORDER["auto"] == 0            # degree order where it applies
     assert s.memory_kind == 0 and not s.dev_alloc and not s.dev_free and not s.alloc_ctx
 
 

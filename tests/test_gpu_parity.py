@@ -135,6 +135,71 @@ def test_partition_long_rows_share_workgroups(tmp_path):
     assert pw.max() <= 1.4 * pw.mean()
 
 
+def _degree_order(p, ranges=512):
+    """The device order of PDHCG_ORDER_DEGREE recomputed from its stated
+    rule: columns by their count of nonzeros in A, longest first (ties in the
+    caller's order); the head (counts >= max(4096, (nnz(A) + nnz(P)) / 512 /
+    8)) in that order; then the rest dealt in turn to the 512 ranges less
+    the head's workgroups (head rows packed in order up to a 1/512 share of
+    the A^T and P nonzeros)."""
+    deg = np.bincount(p.A.indices, minlength=p.n)
+    pnz = np.diff(p.P.tocsr().indptr) if p.P is not None else np.zeros(p.n, dtype=np.int64)
+    order = np.argsort(-deg, kind="stable")
+    share = (p.A.nnz + (p.P.nnz if p.P is not None else 0)) / ranges
+    head = int(np.sum(deg >= max(4096.0, share / 8.0)))
+    bins, cur = 0, 0.0
+    for i in order[:head]:
+        z = float(deg[i] + pnz[i])
+        if cur > 0.0 and cur + z > share:
+            bins, cur = bins + 1, 0.0
+        cur += z
+    bins += head > 0
+    rest = order[head:]
+    R = max(1, min(max(ranges - bins, 1), rest.size))
+    return np.concatenate([order[:head]] + [rest[r::R] for r in range(R)]), head
+
+
+def test_partition_degree_order(tmp_path):
+    """Degree order on the large sparse QP family at n = 1e6: the head of
+    long A^T rows gets workgroups of its own, each a single row or a run of
+    head rows packed up to the average workgroup's A^T-phase nonzeros (A^T
+    row plus P row); the dealt rest gives every other workgroup the same P
+    nonzeros within 1.1x of the mean (the caller's order, with its block of
+    slack columns, allows 1.4x), and A^T-phase nonzeros within 1.5x (the cut
+    balances the weight, in which an A^T nonzero counts 1/3)."""
+    p = synth.large_sparse_qp(seed=2, n=1_000_000, m=500_000)
+    perm, head = _degree_order(p)
+    part = _partition_dump(p, tmp_path, interleave="degree")
+    atn = np.diff(p.A.tocsc().indptr)[perm].astype(float)
+    pn = np.diff(p.P.tocsr().indptr)[perm].astype(float)
+    ph = atn + pn
+    c0, c1 = part[:, 1], part[:, 2]
+    in_head = c1 <= head
+    assert head > 0 and in_head.any()
+    assert np.all(in_head | (c0 >= head))               # no workgroup mixes head and rest
+    ph_w = np.array([ph[a:b].sum() for a, b in zip(c0, c1)])
+    pn_w = np.array([pn[a:b].sum() for a, b in zip(c0, c1)])
+    rest = ~in_head & (c1 > c0)
+    mean_ph = ph_w[rest].mean()
+    for a, b, z in zip(c0[in_head], c1[in_head], ph_w[in_head]):
+        assert b - a == 1 or z <= 1.05 * mean_ph, (a, b, z, mean_ph)
+    print(f"[degree partition] head {head} rows on {in_head.sum()} workgroups; rest: P nnz max/mean "
+          f"{pn_w[rest].max() / pn_w[rest].mean():.3f}, A^T-phase max/mean {ph_w[rest].max() / mean_ph:.3f}",
+          flush=True)
+    assert pn_w[rest].max() <= 1.1 * pn_w[rest].mean()
+    assert ph_w[rest].max() <= 1.5 * mean_ph
+
+
+def test_iterate_parity_degree_order():
+    """The degree order renumbers the coordinates of a cone-free problem on
+    the device; warm starts, iterates and outputs stay in the caller's
+    order and match the oracle."""
+    p = synth.large_sparse_qp(seed=1, n=60_000, m=30_000)
+    rng = np.random.default_rng(3)
+    trace_parity(p, iters=20, interleave="degree", x0=np.abs(rng.standard_normal(p.n)),
+                 y0=rng.standard_normal(p.m))
+
+
 def test_iterate_parity_edge_cones():
     trace_parity(edge_cone_problem())
     trace_parity(edge_cone_problem(1), grid_dim=3)
