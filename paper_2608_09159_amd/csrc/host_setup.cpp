@@ -19,10 +19,52 @@
 #include <cstring>
 #include <iterator>
 #include <numeric>
+#include <thread>
 
 namespace pdhcg {
 
 namespace {
+
+// Loops over rows run on up to 16 host threads, each thread on one
+// contiguous range.  Only work whose result does not depend on the split
+// goes through here (per-row work, elementwise updates, maxima), so the
+// instance is bit-identical for any thread count.
+template <class F>
+void par_rows(int64_t rows, F&& f) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (rows < (int64_t(1) << 16) || hw == 1) {
+    f(int64_t(0), rows);
+    return;
+  }
+  const int64_t chunk = (rows + hw - 1) / hw;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < hw; ++t) {
+    const int64_t a = (int64_t)t * chunk, b = std::min(rows, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([&f, a, b] { f(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// *p = max(*p, v) for the bit patterns of non-negative doubles, which order
+// like the values (so the maximum is the same in any order of updates)
+inline void atomic_max_bits(uint64_t* p, uint64_t v) {
+  uint64_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+  while (v > cur && !__atomic_compare_exchange_n(p, &cur, v, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+  }
+}
+
+inline uint64_t dbits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof u);
+  return u;
+}
+
+inline double bitsd(uint64_t u) {
+  double v;
+  std::memcpy(&v, &u, sizeof v);
+  return v;
+}
 
 int canon_csr(int64_t rows, int64_t cols, const int64_t* ptr, const int32_t* col,
               const double* val, Csr& out) {
@@ -145,20 +187,22 @@ void apply_coord_order(HostInstance& H, std::vector<int>& perm, std::vector<Cone
   // A: renumber columns, keep rows sorted by column
   {
     Csr& A = H.A;
-    std::vector<std::pair<int32_t, double>> row;
-    for (int64_t l = 0; l < A.rows; ++l) {
-      row.clear();
-      for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) row.emplace_back(inv[A.col[k]], A.val[k]);
-      std::sort(row.begin(), row.end(),
-                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                  return a.first < b.first;
-                });
-      int64_t k = A.ptr[l];
-      for (const auto& e : row) {
-        A.col[k] = e.first;
-        A.val[k++] = e.second;
+    par_rows(A.rows, [&](int64_t l0, int64_t l1) {
+      std::vector<std::pair<int32_t, double>> row;
+      for (int64_t l = l0; l < l1; ++l) {
+        row.clear();
+        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) row.emplace_back(inv[A.col[k]], A.val[k]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                    return a.first < b.first;
+                  });
+        int64_t k = A.ptr[l];
+        for (const auto& e : row) {
+          A.col[k] = e.first;
+          A.val[k++] = e.second;
+        }
       }
-    }
+    });
   }
   // P: rows and columns
   if (H.P.rows > 0) {
@@ -168,21 +212,23 @@ void apply_coord_order(HostInstance& H, std::vector<int>& perm, std::vector<Cone
     for (int j = 0; j < n; ++j) Q.ptr[j + 1] = Q.ptr[j] + (H.P.ptr[perm[j] + 1] - H.P.ptr[perm[j]]);
     Q.col.resize(H.P.nnz());
     Q.val.resize(H.P.nnz());
-    std::vector<std::pair<int32_t, double>> row;
-    for (int j = 0; j < n; ++j) {
-      row.clear();
-      const int i = perm[j];
-      for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) row.emplace_back(inv[H.P.col[k]], H.P.val[k]);
-      std::sort(row.begin(), row.end(),
-                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                  return a.first < b.first;
-                });
-      int64_t k = Q.ptr[j];
-      for (const auto& e : row) {
-        Q.col[k] = e.first;
-        Q.val[k++] = e.second;
+    par_rows(n, [&](int64_t j0, int64_t j1) {
+      std::vector<std::pair<int32_t, double>> row;
+      for (int64_t j = j0; j < j1; ++j) {
+        row.clear();
+        const int i = perm[j];
+        for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k) row.emplace_back(inv[H.P.col[k]], H.P.val[k]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                    return a.first < b.first;
+                  });
+        int64_t k = Q.ptr[j];
+        for (const auto& e : row) {
+          Q.col[k] = e.first;
+          Q.val[k++] = e.second;
+        }
       }
-    }
+    });
     H.P = std::move(Q);
   }
   // R columns, c, S_x
@@ -233,9 +279,14 @@ bool degree_order(HostInstance& H, int ranges, double head_nz) {
     for (int i = cb.start; i < cb.start + cb.dim; ++i) type[i] = cb.type;
   std::vector<int64_t> deg(n, 0);
   for (int64_t k = 0; k < H.A.nnz(); ++k) deg[H.A.col[k]]++;
+  // longest first, ties in index order (a counting sort by degree)
+  int64_t dmax = 0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, deg[i]);
+  std::vector<int64_t> start(dmax + 2, 0);
+  for (int i = 0; i < n; ++i) start[dmax - deg[i] + 1]++;
+  for (int64_t d = 0; d <= dmax; ++d) start[d + 1] += start[d];
   std::vector<int> ord(n);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+  for (int i = 0; i < n; ++i) ord[start[dmax - deg[i]]++] = i;
   int head = 0;
   while (head < n && (double)deg[ord[head]] >= head_nz) ++head;
   std::vector<int> perm;
@@ -279,8 +330,10 @@ bool degree_order(HostInstance& H, int ranges, double head_nz) {
 
 // divide entry (l, i) by row[l] * col[i]
 void apply_scaling(Csr& a, const std::vector<double>& row, const std::vector<double>& col) {
-  for (int64_t l = 0; l < a.rows; ++l)
-    for (int64_t k = a.ptr[l]; k < a.ptr[l + 1]; ++k) a.val[k] = a.val[k] / (row[l] * col[a.col[k]]);
+  par_rows(a.rows, [&](int64_t l0, int64_t l1) {
+    for (int64_t l = l0; l < l1; ++l)
+      for (int64_t k = a.ptr[l]; k < a.ptr[l + 1]; ++k) a.val[k] = a.val[k] / (row[l] * col[a.col[k]]);
+  });
 }
 
 }  // namespace
@@ -341,13 +394,30 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   if (hasP) {
     rc = canon_csr(n, n, p.P_rowptr, p.P_col, p.P_val, H.P);
     if (rc) return rc;
-    // symmetry: P == P^T up to a relative 1e-12
-    Csr PT = transpose(H.P);
+    // symmetry: P == P^T up to a relative 1e-12 (every entry (i, j) has a
+    // mirror (j, i) within the tolerance; rows are sorted, without
+    // duplicates)
     double pmax = 0.0;
     for (double v : H.P.val) pmax = std::max(pmax, std::fabs(v));
-    if (PT.ptr != H.P.ptr || PT.col != H.P.col) return PDHCG_E_NONSYM;
-    for (int64_t k = 0; k < H.P.nnz(); ++k)
-      if (std::fabs(PT.val[k] - H.P.val[k]) > 1e-12 * std::max(1.0, pmax)) return PDHCG_E_NONSYM;
+    const double ptol = 1e-12 * std::max(1.0, pmax);
+    const Csr& Pm = H.P;
+    int flag = 0;
+    par_rows(n, [&](int64_t i0, int64_t i1) {
+      bool ok = true;
+      for (int64_t i = i0; i < i1 && ok; ++i)
+        for (int64_t k = Pm.ptr[i]; k < Pm.ptr[i + 1]; ++k) {
+          const int32_t j = Pm.col[k];
+          const int32_t* b0 = Pm.col.data() + Pm.ptr[j];
+          const int32_t* b1 = Pm.col.data() + Pm.ptr[j + 1];
+          const int32_t* it = std::lower_bound(b0, b1, (int32_t)i);
+          if (it == b1 || *it != (int32_t)i || std::fabs(Pm.val[it - Pm.col.data()] - Pm.val[k]) > ptol) {
+            ok = false;
+            break;
+          }
+        }
+      if (!ok) __atomic_store_n(&flag, 1, __ATOMIC_RELAXED);
+    });
+    if (flag) return PDHCG_E_NONSYM;
   } else {
     H.P = Csr();
   }
@@ -423,14 +493,20 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   if (s.scaling) {
     std::vector<double> row(m), col(n);
     for (int it = 0; it < s.ruiz_iters; ++it) {
-      std::fill(row.begin(), row.end(), 0.0);
-      std::fill(col.begin(), col.end(), 0.0);
-      for (int64_t l = 0; l < m; ++l)
-        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
-          double a = std::fabs(A.val[k]);
-          row[l] = std::max(row[l], a);
-          col[A.col[k]] = std::max(col[A.col[k]], a);
+      std::vector<uint64_t> colb(n, dbits(0.0));
+      par_rows(m, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) {
+          double rmax = 0.0;
+          for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
+            const double a = std::fabs(A.val[k]);
+            if (!(a > 0.0)) continue;   // zeros (and NaN) leave both maxima unchanged
+            rmax = std::max(rmax, a);
+            atomic_max_bits(&colb[A.col[k]], dbits(a));
+          }
+          row[l] = rmax;
         }
+      });
+      for (int i = 0; i < n; ++i) col[i] = bitsd(colb[i]);
       for (auto& v : row) v = std::sqrt(v);
       for (auto& v : col) v = std::sqrt(v);
       for (auto& bk : blocks) {
@@ -448,13 +524,24 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
       const double al = s.pc_alpha;
       std::fill(row.begin(), row.end(), 0.0);
       std::fill(col.begin(), col.end(), 0.0);
+      // sums over the nonzeros (an exponent 0 counts them); the column
+      // powers are formed in parallel and summed in row order
+      std::vector<double> cpow(A.nnz());
+      par_rows(m, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l)
+          for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
+            const double a = std::fabs(A.val[k]);
+            if (a == 0.0) {
+              cpow[k] = 0.0;
+              continue;
+            }
+            row[l] += std::pow(a, al);
+            cpow[k] = std::pow(a, 2.0 - al);
+          }
+      });
       for (int64_t l = 0; l < m; ++l)
-        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
-          const double a = std::fabs(A.val[k]);
-          if (a == 0.0) continue;   // sums over the nonzeros (an exponent 0 counts them)
-          row[l] += std::pow(a, al);
-          col[A.col[k]] += std::pow(a, 2.0 - al);
-        }
+        for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k)
+          if (A.val[k] != 0.0) col[A.col[k]] += cpow[k];
       for (auto& v : row) v = std::sqrt(v);
       for (auto& v : col) v = std::sqrt(v);
       for (auto& bk : blocks) {
@@ -482,9 +569,11 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
     H.xhi[i] *= H.Sx[i];
   }
   if (hasP)
-    for (int64_t i = 0; i < n; ++i)
-      for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k)
-        H.P.val[k] = H.P.val[k] / (H.Sx[i] * H.Sx[H.P.col[k]]);
+    par_rows(n, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i)
+        for (int64_t k = H.P.ptr[i]; k < H.P.ptr[i + 1]; ++k)
+          H.P.val[k] = H.P.val[k] / (H.Sx[i] * H.Sx[H.P.col[k]]);
+    });
   for (int a = 0; a < r; ++a)
     for (int i = 0; i < n; ++i) H.R[(size_t)a * n + i] /= H.Sx[i];
   H.nu_b = H.nu_c = 1.0;
