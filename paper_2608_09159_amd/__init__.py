@@ -32,6 +32,11 @@ to the library as device memory (torch CUDA tensors; numpy inputs are moved
 to the device first) and returns x, y, s as torch CUDA tensors;
 ``allocator="torch"`` makes the library take its device memory from torch's
 caching allocator (settings.dev_alloc / dev_free).
+
+``interleave`` takes a name of ORDER (or the PDHCG_ORDER_* value): the
+device's coordinate order; "auto" (the default) picks "degree" for large
+cone-free problems with skewed columns.  Inputs and outputs stay in the
+caller's order either way.
 """
 from __future__ import annotations
 
