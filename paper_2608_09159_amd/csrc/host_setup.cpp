@@ -46,6 +46,34 @@ void par_rows(int64_t rows, F&& f) {
   for (auto& x : th) x.join();
 }
 
+// The same over the rows of a CSR matrix, split so that every thread gets
+// about the same number of nonzeros (rows of very different lengths, such
+// as a Fisher market's buyer and good rows, would otherwise leave one
+// thread with most of the work).
+template <class F>
+void par_rows_nnz(const std::vector<int64_t>& ptr, int64_t rows, F&& f) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nnz = rows > 0 ? ptr[rows] : 0;
+  if (nnz < (int64_t(1) << 18) || hw == 1) {
+    f(int64_t(0), rows);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t a = 0;
+  for (unsigned t = 1; t <= hw && a < rows; ++t) {
+    int64_t b = rows;
+    if (t < hw) {
+      const int64_t target = nnz / hw * t;
+      b = std::upper_bound(ptr.begin(), ptr.begin() + rows + 1, target) - ptr.begin() - 1;
+      b = std::max(b, a + 1);
+      b = std::min(b, rows);
+    }
+    th.emplace_back([&f, a, b] { f(a, b); });
+    a = b;
+  }
+  for (auto& x : th) x.join();
+}
+
 // *p = max(*p, v) for the bit patterns of non-negative doubles, which order
 // like the values (so the maximum is the same in any order of updates)
 inline void atomic_max_bits(uint64_t* p, uint64_t v) {
@@ -102,22 +130,35 @@ int canon_csr(int64_t rows, int64_t cols, const int64_t* ptr, const int32_t* col
   return PDHCG_OK;
 }
 
+// Transpose of a CSR matrix whose rows are sorted by column.  Each output
+// row lists its entries in input-row order, as a serial scatter would; the
+// counts are order-free, and each thread fills a range of output rows by
+// scanning every input row for the columns of its range (binary search in
+// the sorted row), so the result does not depend on the thread count.
 Csr transpose(const Csr& a) {
   Csr t;
   t.rows = a.cols;
   t.cols = a.rows;
   t.ptr.assign(t.rows + 1, 0);
-  for (int64_t k = 0; k < a.nnz(); ++k) t.ptr[a.col[k] + 1]++;
+  par_rows_nnz(a.ptr, a.rows, [&](int64_t l0, int64_t l1) {
+    for (int64_t k = a.ptr[l0]; k < a.ptr[l1]; ++k) __atomic_fetch_add(&t.ptr[a.col[k] + 1], 1, __ATOMIC_RELAXED);
+  });
   for (int64_t i = 0; i < t.rows; ++i) t.ptr[i + 1] += t.ptr[i];
   t.col.resize(a.nnz());
   t.val.resize(a.nnz());
-  std::vector<int64_t> pos(t.ptr.begin(), t.ptr.end() - 1);
-  for (int64_t i = 0; i < a.rows; ++i)
-    for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-      int64_t d = pos[a.col[k]]++;
-      t.col[d] = (int32_t)i;
-      t.val[d] = a.val[k];
+  par_rows_nnz(t.ptr, t.rows, [&](int64_t c0, int64_t c1) {
+    std::vector<int64_t> pos(t.ptr.begin() + c0, t.ptr.begin() + c1);
+    for (int64_t l = 0; l < a.rows; ++l) {
+      const int32_t* b0 = a.col.data() + a.ptr[l];
+      const int32_t* b1 = a.col.data() + a.ptr[l + 1];
+      const int32_t* lo = (c0 == 0) ? b0 : std::lower_bound(b0, b1, (int32_t)c0);
+      for (const int32_t* q = lo; q < b1 && *q < c1; ++q) {
+        const int64_t d = pos[*q - c0]++;
+        t.col[d] = (int32_t)l;
+        t.val[d] = a.val[q - a.col.data()];
+      }
     }
+  });
   return t;
 }
 
@@ -187,7 +228,7 @@ void apply_coord_order(HostInstance& H, std::vector<int>& perm, std::vector<Cone
   // A: renumber columns, keep rows sorted by column
   {
     Csr& A = H.A;
-    par_rows(A.rows, [&](int64_t l0, int64_t l1) {
+    par_rows_nnz(A.ptr, A.rows, [&](int64_t l0, int64_t l1) {
       std::vector<std::pair<int32_t, double>> row;
       for (int64_t l = l0; l < l1; ++l) {
         row.clear();
@@ -330,7 +371,7 @@ bool degree_order(HostInstance& H, int ranges, double head_nz) {
 
 // divide entry (l, i) by row[l] * col[i]
 void apply_scaling(Csr& a, const std::vector<double>& row, const std::vector<double>& col) {
-  par_rows(a.rows, [&](int64_t l0, int64_t l1) {
+  par_rows_nnz(a.ptr, a.rows, [&](int64_t l0, int64_t l1) {
     for (int64_t l = l0; l < l1; ++l)
       for (int64_t k = a.ptr[l]; k < a.ptr[l + 1]; ++k) a.val[k] = a.val[k] / (row[l] * col[a.col[k]]);
   });
@@ -492,9 +533,10 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
   Csr& A = H.A;
   if (s.scaling) {
     std::vector<double> row(m), col(n);
+    std::vector<uint64_t> colb(n);
     for (int it = 0; it < s.ruiz_iters; ++it) {
-      std::vector<uint64_t> colb(n, dbits(0.0));
-      par_rows(m, [&](int64_t l0, int64_t l1) {
+      par_rows(n, [&](int64_t i0, int64_t i1) { std::fill(colb.begin() + i0, colb.begin() + i1, dbits(0.0)); });
+      par_rows_nnz(A.ptr, m, [&](int64_t l0, int64_t l1) {
         for (int64_t l = l0; l < l1; ++l) {
           double rmax = 0.0;
           for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
@@ -506,19 +548,30 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
           row[l] = rmax;
         }
       });
-      for (int i = 0; i < n; ++i) col[i] = bitsd(colb[i]);
-      for (auto& v : row) v = std::sqrt(v);
-      for (auto& v : col) v = std::sqrt(v);
+      par_rows(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) col[i] = std::sqrt(bitsd(colb[i]));
+      });
+      par_rows(m, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) row[l] = std::sqrt(row[l]);
+      });
       for (auto& bk : blocks) {
         double mx = 0.0;
         for (int i = bk.first; i < bk.first + bk.second; ++i) mx = std::max(mx, col[i]);
         for (int i = bk.first; i < bk.first + bk.second; ++i) col[i] = mx;
       }
-      for (auto& v : row) if (v == 0.0) v = 1.0;
-      for (auto& v : col) if (v == 0.0) v = 1.0;
+      par_rows(m, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) if (row[l] == 0.0) row[l] = 1.0;
+      });
+      par_rows(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) if (col[i] == 0.0) col[i] = 1.0;
+      });
       apply_scaling(A, row, col);
-      for (int l = 0; l < m; ++l) H.Sy[l] /= row[l];
-      for (int i = 0; i < n; ++i) H.Sx[i] *= col[i];
+      par_rows(m, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) H.Sy[l] /= row[l];
+      });
+      par_rows(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) H.Sx[i] *= col[i];
+      });
     }
     if (s.pock_chambolle) {
       const double al = s.pc_alpha;
@@ -527,7 +580,7 @@ int build_instance(const pdhcg_problem& p, const pdhcg_settings& s, HostInstance
       // sums over the nonzeros (an exponent 0 counts them); the column
       // powers are formed in parallel and summed in row order
       std::vector<double> cpow(A.nnz());
-      par_rows(m, [&](int64_t l0, int64_t l1) {
+      par_rows_nnz(A.ptr, m, [&](int64_t l0, int64_t l1) {
         for (int64_t l = l0; l < l1; ++l)
           for (int64_t k = A.ptr[l]; k < A.ptr[l + 1]; ++k) {
             const double a = std::fabs(A.val[k]);

@@ -200,6 +200,26 @@ def test_iterate_parity_degree_order():
                  y0=rng.standard_normal(p.m))
 
 
+def test_iterate_parity_degree_order_mixed_types():
+    """The degree order forced on a cone-free problem that mixes box, R+ and
+    free coordinates with two-sided rows and a low-rank Q: each coordinate
+    keeps its type (runs of one type become blocks) and its box bounds, and
+    warm starts, iterates and outputs stay in the caller's order."""
+    p = synth.bounded_qp(seed=3)
+    cones = [(k if k in ("box", "nonneg", "free") else "free", st, d, 0.0) for k, st, d, al in p.cones]
+    q = Problem(n=p.n, m=p.m, A=p.A, b=p.b, c=p.c, P=p.P, R=p.R, D=p.D, cones=cones, row_lo=p.row_lo,
+                row_hi=p.row_hi, x_lo=p.x_lo, x_hi=p.x_hi, name="bounded_cone_free")
+    rng = np.random.default_rng(4)
+    trace_parity(q, iters=30, interleave="degree", grid_dim=4, x0=rng.standard_normal(q.n),
+                 y0=rng.standard_normal(q.m))
+
+
+def test_degree_order_keeps_cone_problems_in_caller_order():
+    """Problems with cone blocks are left in the caller's order by the
+    degree setting (the order is for cone-free problems only)."""
+    trace_parity(synth.tiny_mixed(4), iters=20, interleave="degree")
+
+
 def test_iterate_parity_edge_cones():
     trace_parity(edge_cone_problem())
     trace_parity(edge_cone_problem(1), grid_dim=3)
