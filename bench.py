@@ -23,8 +23,8 @@ cpu_baseline: the oracle as it stands, one thread, on the first outer
 iterations of the same instance, run in a child process started before the
 GPU work (its setup, which is not timed, overlaps the GPU runs).
 
-Prints one JSON line.  `--gpus N` with N > 1 is rejected: this build targets a
-single GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is rejected: the solver runs on
+one GPU.
 """
 from __future__ import annotations
 

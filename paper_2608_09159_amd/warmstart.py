@@ -4,7 +4,7 @@ The paper has no learned component; this is the library's own production
 pattern.  For a family of problems that differ only in their parameters, a
 network maps the parameters to the solver's primal-dual solution; its
 prediction seeds pdhcg_solve, which still runs to the same tolerance, so the
-plain cold-started method remains the fallback and the judge of accuracy.
+plain cold-started method remains the fallback and sets the accuracy.
 
 Family: the quasilinear Fisher market in exponential-cone form on a fixed
 valuation graph (buyers x goods, edges E).  An instance is (u on E, budgets
