@@ -200,6 +200,28 @@ def test_iterate_parity_degree_order():
                  y0=rng.standard_normal(p.m))
 
 
+def test_setup_is_deterministic():
+    """The host setup runs its row loops on several threads (maxima by
+    atomic updates, transposes by column ranges); two setups of the same
+    instance in the degree order give bit-identical scalings, step sizes and
+    iterates."""
+    p = synth.large_sparse_qp(seed=2, n=1_000_000, m=500_000)
+    out = []
+    for _ in range(2):
+        h = G.setup(p, max_iter=16, check_every=4, interleave="degree")
+        try:
+            out.append((h.scaling(), h.solve()))
+        finally:
+            h.free()
+    (sa, ra), (sb, rb) = out
+    for key in ("Sx", "Sy"):
+        assert np.array_equal(sa[key], sb[key]), key
+    for key in ("nu_b", "nu_c", "eta", "omega0"):
+        assert sa[key] == sb[key], key
+    for key in ("x", "y"):
+        assert np.array_equal(ra[key], rb[key]), key
+
+
 def test_iterate_parity_degree_order_mixed_types():
     """The degree order forced on a cone-free problem that mixes box, R+ and
     free coordinates with two-sided rows and a low-rank Q: each coordinate
