@@ -19,11 +19,24 @@
 #include <cstring>
 #include <iterator>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 namespace pdhcg {
 
 namespace {
+
+// Start f(a, b) on a new thread; false (nothing started) when the system
+// refuses one, so that the caller can run the work itself.
+template <class F>
+bool spawn(std::vector<std::thread>& th, F& f, int64_t a, int64_t b) {
+  try {
+    th.emplace_back([&f, a, b] { f(a, b); });
+    return true;
+  } catch (const std::system_error&) {
+    return false;
+  }
+}
 
 // Loops over rows run on up to 16 host threads, each thread on one
 // contiguous range.  Only work whose result does not depend on the split
@@ -38,10 +51,14 @@ void par_rows(int64_t rows, F&& f) {
   }
   const int64_t chunk = (rows + hw - 1) / hw;
   std::vector<std::thread> th;
+  th.reserve(hw);
   for (unsigned t = 0; t < hw; ++t) {
     const int64_t a = (int64_t)t * chunk, b = std::min(rows, a + chunk);
     if (a >= b) break;
-    th.emplace_back([&f, a, b] { f(a, b); });
+    if (!spawn(th, f, a, b)) {   // no thread to be had: the rest runs here
+      f(a, rows);
+      break;
+    }
   }
   for (auto& x : th) x.join();
 }
@@ -68,7 +85,10 @@ void par_rows_nnz(const std::vector<int64_t>& ptr, int64_t rows, F&& f) {
       b = std::max(b, a + 1);
       b = std::min(b, rows);
     }
-    th.emplace_back([&f, a, b] { f(a, b); });
+    if (!spawn(th, f, a, b)) {   // no thread to be had: the rest runs here
+      f(a, rows);
+      break;
+    }
     a = b;
   }
   for (auto& x : th) x.join();
