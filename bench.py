@@ -455,13 +455,14 @@ def solver_kernel_name(prob, precision, grid):
     or, without cone blocks, the cone-free kernel at two workgroups per CU."""
     kinds = {k for k, _, _, _ in prob.cones}
     ext = getattr(prob, "row_lo", None) is not None or bool(kinds & {"box", "exp1"})
+    cones = bool(kinds & {"soc", "rsoc", "exp", "pow", "exp1"})
     if precision == "fp32":
         return "solve_kernel_f32_ext" if ext else "solve_kernel_f32"
     if grid == 1:
         return "solve_kernel_one_ext" if ext else "solve_kernel_one"
     if ext:
-        return "solve_kernel_ext"
-    return "solve_kernel" if kinds & {"soc", "rsoc", "exp", "pow"} else "solve_kernel_lin"
+        return "solve_kernel_ext" if cones else "solve_kernel_lin_ext"
+    return "solve_kernel" if cones else "solve_kernel_lin"
 
 
 def rel_kkt(r):

@@ -336,7 +336,7 @@ int upload_instance(Handle* h, Instance* I) {
   // this solve runs (two per CU for problems without cone blocks)
   const bool fp32 = h->s.precision == PDHCG_PREC_FP32;
   const bool has_cones = !H.wave_start.empty() || !H.lane_start.empty();
-  bool lin_kernel = false;    // the solve runs solve_kernel_lin (set with the grid)
+  bool lin_kernel = false;    // the solve runs solve_kernel_lin(_ext) (set with the grid)
   int maxg = 1;
   HIPCHK(max_resident_grid_for(fp32, P.ext != 0, has_cones, 0, &maxg));
   int G = h->s.grid_dim;
@@ -350,7 +350,7 @@ int upload_instance(Handle* h, Instance* I) {
   }
   G = std::max(1, std::min(G, maxg));
   I->grid = G;
-  lin_kernel = !fp32 && P.ext == 0 && !has_cones && G > 1;
+  lin_kernel = !fp32 && !has_cones && G > 1;
   // ownership ranges: coordinates weighted by their share of the A^T and P
   // passes, the dense factor and the cone projections (cone blocks are never
   // split); rows by their nonzeros

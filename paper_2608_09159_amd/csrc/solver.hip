@@ -1643,6 +1643,9 @@ __global__ __launch_bounds__(BLOCK) void solve_kernel_ext(KArgs A) { solve_body<
 // without the projection code, at 4 waves per SIMD (two workgroups per CU),
 // so twice the gathers of the latency-bound products are in flight
 __global__ __launch_bounds__(BLOCK, 4) void solve_kernel_lin(KArgs A) { solve_body<double, false, false, false>(A); }
+// the same with row bounds and boxes (no fixed-middle EXP blocks: those are
+// cone items)
+__global__ __launch_bounds__(BLOCK, 4) void solve_kernel_lin_ext(KArgs A) { solve_body<double, false, true, false>(A); }
 
 // FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
 __global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false, false>(A); }
@@ -2007,7 +2010,7 @@ int block_size() { return BLOCK; }
 static const void* solver_kernel_for(bool fp32, bool ext, bool cones, int grid) {
   if (fp32) return ext ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32;
   if (grid == 1) return ext ? (const void*)solve_kernel_one_ext : (const void*)solve_kernel_one;
-  if (ext) return (const void*)solve_kernel_ext;
+  if (ext) return cones ? (const void*)solve_kernel_ext : (const void*)solve_kernel_lin_ext;
   return cones ? (const void*)solve_kernel : (const void*)solve_kernel_lin;
 }
 

@@ -1,7 +1,8 @@
 """GPU parity of the implementation form (eq. solver-input): two-sided row
 bounds and box blocks, through the C ABI against the oracle.  Iterates of
 the first 50 iterations to 1e-10 (single workgroup, several workgroups,
-diagonal, low-rank and zero Q, averaged epochs), whole solves with equal
+diagonal, low-rank and zero Q, averaged epochs, with and without cone blocks:
+the cone-free instances run the cone-free kernel), whole solves with equal
 counts, and a batch mixing bounded and equality instances."""
 import numpy as np
 import pytest
@@ -21,6 +22,10 @@ CASES = [
     ("lowrank_grid5", lambda: synth.bounded_qp(4), {"grid_dim": 5}),
     ("large_grid", lambda: synth.bounded_qp(3, n_box=3000, n_cone_soc=40, n_exp=20, m=1500, density=0.004), {}),
     ("avg", lambda: synth.bounded_qp(5, q="diag"), {"scheme": "avg", "avg_epoch": 8}),
+    # without cone blocks: the cone-free kernel with the implementation form
+    ("cone_free_grid4", lambda: synth.bounded_qp(9, n_cone_soc=0, n_exp=0), {"grid_dim": 4}),
+    ("cone_free_lp_large", lambda: synth.bounded_qp(10, n_box=3000, n_cone_soc=0, n_exp=0, m=1500,
+                                                     density=0.004, q=None), {}),
 ]
 
 
@@ -33,6 +38,7 @@ def test_bounded_iterate_parity(name, make, kw):
     ("lowrank", lambda: synth.bounded_qp(0)),
     ("lp", lambda: synth.bounded_qp(2, q=None)),
     ("large", lambda: synth.bounded_qp(3, n_box=3000, n_cone_soc=40, n_exp=20, m=1500, density=0.004)),
+    ("cone_free_large", lambda: synth.bounded_qp(11, n_box=3000, n_cone_soc=0, n_exp=0, m=1500, density=0.004)),
 ])
 def test_bounded_final_parity(name, make):
     p = make()
