@@ -457,7 +457,7 @@ def solver_kernel_name(prob, precision, grid):
     ext = getattr(prob, "row_lo", None) is not None or bool(kinds & {"box", "exp1"})
     cones = bool(kinds & {"soc", "rsoc", "exp", "pow", "exp1"})
     if precision == "fp32":
-        return "solve_kernel_f32_ext" if ext else "solve_kernel_f32"
+        return "solve_kernel_f32" + ("" if cones else "_lin") + ("_ext" if ext else "")
     if grid == 1:
         return "solve_kernel_one_ext" if ext else "solve_kernel_one"
     if ext:

@@ -350,7 +350,7 @@ int upload_instance(Handle* h, Instance* I) {
   }
   G = std::max(1, std::min(G, maxg));
   I->grid = G;
-  lin_kernel = !fp32 && !has_cones && G > 1;
+  lin_kernel = !has_cones && G > 1;
   // ownership ranges: coordinates weighted by their share of the A^T and P
   // passes, the dense factor and the cone projections (cone blocks are never
   // split); rows by their nonzeros

@@ -1650,6 +1650,10 @@ __global__ __launch_bounds__(BLOCK, 4) void solve_kernel_lin_ext(KArgs A) { solv
 // FP32 bulk sweeps (FP32 copies of A, A^T, P, R); everything else as above
 __global__ __launch_bounds__(BLOCK) void solve_kernel_f32(KArgs A) { solve_body<float, false, false>(A); }
 __global__ __launch_bounds__(BLOCK) void solve_kernel_f32_ext(KArgs A) { solve_body<float, false, true>(A); }
+// and without cone blocks, at two workgroups per CU like the FP64 cone-free
+// kernels (the FP64 polish runs those on the same grid)
+__global__ __launch_bounds__(BLOCK, 4) void solve_kernel_f32_lin(KArgs A) { solve_body<float, false, false, false>(A); }
+__global__ __launch_bounds__(BLOCK, 4) void solve_kernel_f32_lin_ext(KArgs A) { solve_body<float, false, true, false>(A); }
 
 // a grid of one workgroup: workgroup barriers and the single-workgroup
 // reductions of the batch kernels (the same arithmetic as a batch solve)
@@ -2008,7 +2012,10 @@ int block_size() { return BLOCK; }
 // the solver kernel of a launch: FP32 bulk or FP64, a grid of one
 // workgroup, the EXT features, problems without cone blocks
 static const void* solver_kernel_for(bool fp32, bool ext, bool cones, int grid) {
-  if (fp32) return ext ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32;
+  if (fp32) {
+    if (ext) return cones ? (const void*)solve_kernel_f32_ext : (const void*)solve_kernel_f32_lin_ext;
+    return cones ? (const void*)solve_kernel_f32 : (const void*)solve_kernel_f32_lin;
+  }
   if (grid == 1) return ext ? (const void*)solve_kernel_one_ext : (const void*)solve_kernel_one;
   if (ext) return cones ? (const void*)solve_kernel_ext : (const void*)solve_kernel_lin_ext;
   return cones ? (const void*)solve_kernel : (const void*)solve_kernel_lin;

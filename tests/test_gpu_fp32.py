@@ -24,17 +24,22 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), 1e-300)
 
 
-@pytest.mark.parametrize("make", [lambda: synth.mixed_cone_scaled(seed=0, scale=0.01),
-                                  lambda: synth.tiny_qp(1),
-                                  lambda: synth.fisher(seed=3, n_buyers=60, n_goods=30, density=0.2)],
-                         ids=["mixed_cone_1k", "tiny_qp", "fisher_60x30"])
-def test_fp32_first_iterations_error_report(make):
+@pytest.mark.parametrize("make,grid", [(lambda: synth.mixed_cone_scaled(seed=0, scale=0.01), 0),
+                                       (lambda: synth.tiny_qp(1), 0),
+                                       (lambda: synth.fisher(seed=3, n_buyers=60, n_goods=30, density=0.2), 0),
+                                       (lambda: synth.large_sparse_qp(seed=1, n=60_000, m=30_000), 0),
+                                       (lambda: synth.bounded_qp(9, n_cone_soc=0, n_exp=0), 4)],
+                         ids=["mixed_cone_1k", "tiny_qp", "fisher_60x30", "large_sparse_qp_60k",
+                              "cone_free_bounded_grid4"])
+def test_fp32_first_iterations_error_report(make, grid):
     """First 20 iterations (fixed inner count, one check) of the FP32 phase
-    against the FP64 oracle: relative error of every iterate below 1e-4."""
+    against the FP64 oracle: relative error of every iterate below 1e-4
+    (cone-free problems on several workgroups run the FP32 cone-free
+    kernels)."""
     p = make()
     iters = 20
     kw = dict(trace_iters=iters, max_iter=iters, check_every=64, fixed_inner=3)
-    h = G.setup(p, precision="fp32", **kw)
+    h = G.setup(p, precision="fp32", grid_dim=grid, **kw)
     try:
         h.solve()
         tr = h.trace(iters)
@@ -50,13 +55,14 @@ def test_fp32_first_iterations_error_report(make):
     assert worst <= 1e-4
 
 
-@pytest.mark.parametrize("make", [lambda: synth.mixed_cone_scaled(seed=0, scale=0.004),
-                                  lambda: synth.tiny_qp(0),
-                                  lambda: synth.fisher(seed=7, n_buyers=50, n_goods=20, density=0.25)],
-                         ids=["mixed_cone", "tiny_qp", "fisher"])
-def test_fp32_polished_solve_matches_oracle(make):
+@pytest.mark.parametrize("make,grid", [(lambda: synth.mixed_cone_scaled(seed=0, scale=0.004), 0),
+                                       (lambda: synth.tiny_qp(0), 0),
+                                       (lambda: synth.fisher(seed=7, n_buyers=50, n_goods=20, density=0.25), 0),
+                                       (lambda: synth.bounded_qp(12, n_cone_soc=0, n_exp=0), 4)],
+                         ids=["mixed_cone", "tiny_qp", "fisher", "cone_free_bounded_grid4"])
+def test_fp32_polished_solve_matches_oracle(make, grid):
     p = make()
-    g = G.solve(p, precision="fp32", fp32_tol=1e-4, max_iter=200000)
+    g = G.solve(p, precision="fp32", fp32_tol=1e-4, max_iter=200000, grid_dim=grid)
     o = pdhg.solve(p, oracle_settings(max_iter=200000))
     dx = np.linalg.norm(g["x"] - o.x) / max(np.linalg.norm(o.x), 1e-300)
     print(f"[fp32] {p.name}: {g['iterations']} it ({g['polish_iterations']} FP64 polish), "
