@@ -51,11 +51,11 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "large_sparse_qp", "grid": 512, "iterations": 256,
-    "sources_sha256": "acce6a146d57d2963be0fb698507dc847be1a3d87b0d8991f76d364b752f0a7d",
-    # FETCH_SIZE 3,561,709,275.4 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 478,547,211.4 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
+    "sources_sha256": "d804fdeaecb6792eb7626dd632d0a6b88bb8eca55f316c863aa5d2ab5aa685fb",
+    # FETCH_SIZE 3,563,413,267.4 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 478,552,569.9 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
     # (degree coordinate order)
-    "bytes_per_launch": 7783449597665.2,
+    "bytes_per_launch": 7786958315436.2,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
