@@ -131,3 +131,25 @@ def edge_cone_problem(seed=0, m=9):
                    cones=cones, name="edge_cones")
 
 
+def degree_order_rule(p, ranges=512):
+    """The device order of PDHCG_ORDER_DEGREE recomputed from its stated
+    rule: columns by their count of nonzeros in A, longest first (ties in the
+    caller's order); the head (counts >= max(4096, (nnz(A) + nnz(P)) / 512 /
+    8)) in that order; then the rest dealt in turn to the 512 ranges less
+    the head's workgroups (head rows packed in order up to a 1/512 share of
+    the A^T and P nonzeros)."""
+    deg = np.bincount(p.A.indices, minlength=p.n)
+    pnz = np.diff(p.P.tocsr().indptr) if p.P is not None else np.zeros(p.n, dtype=np.int64)
+    order = np.argsort(-deg, kind="stable")
+    share = (p.A.nnz + (p.P.nnz if p.P is not None else 0)) / ranges
+    head = int(np.sum(deg >= max(4096.0, share / 8.0)))
+    bins, cur = 0, 0.0
+    for i in order[:head]:
+        z = float(deg[i] + pnz[i])
+        if cur > 0.0 and cur + z > share:
+            bins, cur = bins + 1, 0.0
+        cur += z
+    bins += head > 0
+    rest = order[head:]
+    R = max(1, min(max(ranges - bins, 1), rest.size))
+    return np.concatenate([order[:head]] + [rest[r::R] for r in range(R)]), head

@@ -14,7 +14,7 @@ import scipy.sparse as sp
 
 import paper_2608_09159_amd as G
 from instances import Problem, synth
-from parity_util import edge_cone_problem, final_parity, recheck_kkt, trace_parity
+from parity_util import degree_order_rule, edge_cone_problem, final_parity, recheck_kkt, trace_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -135,30 +135,6 @@ def test_partition_long_rows_share_workgroups(tmp_path):
     assert pw.max() <= 1.4 * pw.mean()
 
 
-def _degree_order(p, ranges=512):
-    """The device order of PDHCG_ORDER_DEGREE recomputed from its stated
-    rule: columns by their count of nonzeros in A, longest first (ties in the
-    caller's order); the head (counts >= max(4096, (nnz(A) + nnz(P)) / 512 /
-    8)) in that order; then the rest dealt in turn to the 512 ranges less
-    the head's workgroups (head rows packed in order up to a 1/512 share of
-    the A^T and P nonzeros)."""
-    deg = np.bincount(p.A.indices, minlength=p.n)
-    pnz = np.diff(p.P.tocsr().indptr) if p.P is not None else np.zeros(p.n, dtype=np.int64)
-    order = np.argsort(-deg, kind="stable")
-    share = (p.A.nnz + (p.P.nnz if p.P is not None else 0)) / ranges
-    head = int(np.sum(deg >= max(4096.0, share / 8.0)))
-    bins, cur = 0, 0.0
-    for i in order[:head]:
-        z = float(deg[i] + pnz[i])
-        if cur > 0.0 and cur + z > share:
-            bins, cur = bins + 1, 0.0
-        cur += z
-    bins += head > 0
-    rest = order[head:]
-    R = max(1, min(max(ranges - bins, 1), rest.size))
-    return np.concatenate([order[:head]] + [rest[r::R] for r in range(R)]), head
-
-
 def test_partition_degree_order(tmp_path):
     """Degree order on the large sparse QP family at n = 1e6: the head of
     long A^T rows gets workgroups of its own, each a single row or a run of
@@ -168,7 +144,7 @@ def test_partition_degree_order(tmp_path):
     slack columns, allows 1.4x), and A^T-phase nonzeros within 1.5x (the cut
     balances the weight, in which an A^T nonzero counts 1/3)."""
     p = synth.large_sparse_qp(seed=2, n=1_000_000, m=500_000)
-    perm, head = _degree_order(p)
+    perm, head = degree_order_rule(p)
     part = _partition_dump(p, tmp_path, interleave="degree")
     atn = np.diff(p.A.tocsc().indptr)[perm].astype(float)
     pn = np.diff(p.P.tocsr().indptr)[perm].astype(float)
