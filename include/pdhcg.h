@@ -297,7 +297,9 @@ int pdhcg_default_settings(pdhcg_settings* s);
 /* Validate `count` problems, rescale them (Section "Problem Rescaling"),
  * build A^T, estimate ||A^||_2 (eq. practical-stepsizes), upload everything
  * to the current HIP device and return a handle in *out.  count > 1 prepares
- * a batch for pdhcg_solve_batch.  On error *out is left NULL.               */
+ * a batch for pdhcg_solve_batch.  On error *out is left NULL.
+ * The host part runs on up to 16 threads (fewer if the environment variable
+ * PDHCG_HOST_THREADS says so); its result does not depend on their number. */
 int pdhcg_setup(const pdhcg_problem* probs, int32_t count,
                 const pdhcg_settings* s, pdhcg_handle** out);
 

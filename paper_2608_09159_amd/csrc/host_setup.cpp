@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <iterator>
 #include <numeric>
@@ -38,13 +39,25 @@ bool spawn(std::vector<std::thread>& th, F& f, int64_t a, int64_t b) {
   }
 }
 
+// Host threads for the setup loops: the CPUs the system reports, at most 16,
+// or fewer when the environment variable PDHCG_HOST_THREADS asks for fewer
+// (1 runs every loop on the calling thread).
+unsigned host_threads() {
+  unsigned t = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("PDHCG_HOST_THREADS")) {
+    const int k = std::atoi(e);
+    if (k >= 1) t = std::min<unsigned>(t, (unsigned)k);
+  }
+  return t;
+}
+
 // Loops over rows run on up to 16 host threads, each thread on one
 // contiguous range.  Only work whose result does not depend on the split
 // goes through here (per-row work, elementwise updates, maxima), so the
 // instance is bit-identical for any thread count.
 template <class F>
 void par_rows(int64_t rows, F&& f) {
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned hw = host_threads();
   if (rows < (int64_t(1) << 16) || hw == 1) {
     f(int64_t(0), rows);
     return;
@@ -69,7 +82,7 @@ void par_rows(int64_t rows, F&& f) {
 // thread with most of the work).
 template <class F>
 void par_rows_nnz(const std::vector<int64_t>& ptr, int64_t rows, F&& f) {
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned hw = host_threads();
   const int64_t nnz = rows > 0 ? ptr[rows] : 0;
   if (nnz < (int64_t(1) << 18) || hw == 1) {
     f(int64_t(0), rows);

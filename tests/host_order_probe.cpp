@@ -1,7 +1,7 @@
 // Host-side probe of the library's problem setup for the CPU tests: reads a
 // problem from raw little-endian files, runs pdhcg::build_instance with the
 // given settings.interleave, and writes the device coordinate order (perm),
-// the head length and the column structure of the renumbered A.
+// the head length, the renumbered and rescaled matrices and the scaling.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -59,6 +59,21 @@ int main(int argc, char** argv) {
   write_all(d + "/perm", H.perm);
   write_all(d + "/A_out_ptr", H.A.ptr);
   write_all(d + "/A_out_col", H.A.col);
+  // everything else the setup computes, for the thread-count check
+  write_all(d + "/A_out_val", H.A.val);
+  write_all(d + "/AT_out_ptr", H.AT.ptr);
+  write_all(d + "/AT_out_col", H.AT.col);
+  write_all(d + "/AT_out_val", H.AT.val);
+  write_all(d + "/P_out_ptr", H.P.ptr);
+  write_all(d + "/P_out_col", H.P.col);
+  write_all(d + "/P_out_val", H.P.val);
+  write_all(d + "/Sx_out", H.Sx);
+  write_all(d + "/Sy_out", H.Sy);
+  write_all(d + "/b_out", H.b);
+  write_all(d + "/c_out", H.c);
+  write_all(d + "/qdiag_out", H.qdiag);
+  const double nu[2] = {H.nu_b, H.nu_c};
+  write_all(d + "/nu_out", std::vector<double>(nu, nu + 2));
   std::printf("%d %d\n", rc, H.head);
   return 0;
 }

@@ -2,7 +2,8 @@
 PDHCG_ORDER_*): the library's host code (host_setup.cpp, compiled here with
 g++ and a small probe) against the order recomputed from its stated rule
 (parity_util.degree_order_rule), on the large sparse QP family (power-law
-column degrees, slack columns, sparse P) at n = 2e5."""
+column degrees, slack columns, sparse P) at n = 2e5; and every array the
+setup computes compared byte for byte between 1 and 8 host threads."""
 import os
 import shutil
 import subprocess
@@ -46,8 +47,16 @@ def problem(tmp_path_factory):
     return p, str(d)
 
 
-def _run(probe, d, order):
-    out = subprocess.run([probe, d, str(order)], check=True, capture_output=True, text=True).stdout.split()
+OUTPUTS = ("perm", "A_out_ptr", "A_out_col", "A_out_val", "AT_out_ptr", "AT_out_col", "AT_out_val",
+           "P_out_ptr", "P_out_col", "P_out_val", "Sx_out", "Sy_out", "b_out", "c_out", "qdiag_out", "nu_out")
+
+
+def _run(probe, d, order, threads=None):
+    env = dict(os.environ)
+    if threads is not None:
+        env["PDHCG_HOST_THREADS"] = str(threads)
+    out = subprocess.run([probe, d, str(order)], check=True, capture_output=True, text=True,
+                         env=env).stdout.split()
     perm = np.fromfile(os.path.join(d, "perm"), dtype=np.int32)
     ptr = np.fromfile(os.path.join(d, "A_out_ptr"), dtype=np.int64)
     col = np.fromfile(os.path.join(d, "A_out_col"), dtype=np.int32)
@@ -77,3 +86,17 @@ def test_caller_and_auto_orders_keep_small_problems_in_place(probe, problem):
         rc, head, perm, ptr, col = _run(probe, d, order)
         assert rc == 0 and head == 0 and perm.size == 0
         assert np.array_equal(col, p.A.indices)
+
+
+@pytest.mark.parametrize("order", [2, -1])
+def test_setup_is_bit_identical_for_any_thread_count(probe, problem, order):
+    """The host setup's threaded loops (scaling maxima, powers, renumbering,
+    transpose) give the same bytes on 1 thread and on 8."""
+    p, d = problem
+    got = {}
+    for threads in (1, 8):
+        assert _run(probe, d, order, threads)[0] == 0
+        got[threads] = {f: open(os.path.join(d, f), "rb").read() for f in OUTPUTS}
+    for f in OUTPUTS:
+        assert got[1][f] == got[8][f], f
+    assert len(got[1]["AT_out_col"]) == 4 * p.A.nnz
