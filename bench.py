@@ -51,11 +51,11 @@ BF16_DENSE_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 # iteration count; otherwise (and while None) the bench reports null.
 MEASURED_TRAFFIC = {
     "workload": "large_sparse_qp", "grid": 512, "iterations": 256,
-    "sources_sha256": "d804fdeaecb6792eb7626dd632d0a6b88bb8eca55f316c863aa5d2ab5aa685fb",
-    # FETCH_SIZE 3,563,413,267.4 KiB x 1.99974 (copy calibration) + WRITE_SIZE
-    # 478,552,569.9 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
+    "sources_sha256": "ada668ab3d6c519d6e411bf50b7f4fc254eddc242767f17a5bab3e6c08f8bb37",
+    # FETCH_SIZE 3,561,594,958.7 KiB x 1.99974 (copy calibration) + WRITE_SIZE
+    # 478,528,850.6 KiB x 1.0, per 256-iteration launch of solve_kernel_lin
     # (degree coordinate order)
-    "bytes_per_launch": 7786958315436.2,
+    "bytes_per_launch": 7783200183547.8,
 }
 KERNEL_SOURCES = ("solver.hip", "cones.hpp", "common.hpp", "api.cpp", "host_setup.cpp")
 
